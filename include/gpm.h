@@ -1,0 +1,274 @@
+/*
+ * gpm.h -- exact subgraph counting on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: pattern-aware depth-first subgraph extension (Chen & Arvind,
+ * "Efficient and Scalable Graph Pattern Mining on GPUs", OSDI'22 /
+ * arXiv 2112.09761).  A partial match is extended one pattern vertex at a
+ * time by intersecting / subtracting sorted neighbour lists under the
+ * pattern's matching order and symmetry order (Sec. 2.2, "Pattern-Aware GPM
+ * Algorithms"; Alg. 1), and the exact match count is reduced at the leaves.
+ *
+ * Conventions shared by every entry point
+ *   - Functions never abort and never print.  They return GPM_OK (0) or a
+ *     negative gpm_status; outputs are written only on GPM_OK.
+ *     gpm_last_error() describes the last failure on a context.
+ *   - A context is bound to one device and is not thread-safe: use it from
+ *     one host thread at a time.
+ *   - Counts are exact unsigned 64-bit integers.  The device adds partial
+ *     counts modulo 2^64, so any summation order gives the same bits; no
+ *     shipped workload comes near 2^64.
+ *   - Graph vertices are 0..n-1 (int32 ids, so n < 2^31); adjacency offsets
+ *     are int64.
+ *   - Pattern vertices are 0..k-1 with 1 <= k <= 8; a pattern must be
+ *     connected (vertex extension only grows connected subgraphs, Sec. 2.2).
+ */
+#ifndef GPM_H
+#define GPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gpm_ctx gpm_ctx;
+typedef int32_t gpm_status;
+
+enum {
+    GPM_OK = 0,
+    GPM_E_INVAL = -1,        /* bad argument (null pointer, bad id, bad size) */
+    GPM_E_CSR = -2,          /* CSR not canonical: unsorted / duplicate
+                                neighbours, self loop, id out of range, or
+                                asymmetric when GPM_VALIDATE asks to check */
+    GPM_E_PATTERN = -3,      /* k < 1, k > 8, bad edge, disconnected pattern */
+    GPM_E_NOMEM = -4,        /* device memory budget too small */
+    GPM_E_DEVICE = -5,       /* a HIP runtime call failed */
+    GPM_E_UNSUPPORTED = -6,  /* e.g. a non-clique pattern on a DAG-only graph */
+    GPM_E_BUSY = -7,         /* no serving slot free; retry after gpm_poll */
+    GPM_E_TIMEOUT = -8       /* gpm_wait timed out; the query is still live */
+};
+
+/* Induced-ness of a match (Sec. 2.1 "GPM Problems"): vertex-induced is the
+ * default of the paper's API; edge-induced is subgraph listing's. */
+enum { GPM_VERTEX_INDUCED = 0, GPM_EDGE_INDUCED = 1 };
+
+/* gpm_load_csr flags */
+enum {
+    GPM_CSR_SYMMETRIC = 1,   /* every edge stored in both directions        */
+    GPM_CSR_DAG = 2,         /* already oriented (each edge once): cliques
+                                only (orientation, Sec. 3, graph loader)     */
+    GPM_PTRS_DEVICE = 4,     /* row_ptr / col are device pointers on the
+                                context's device (e.g. torch data_ptr())     */
+    GPM_VALIDATE = 8         /* also check symmetry, O(m log d) on the host  */
+};
+
+#define GPM_MAX_K 8
+#define GPM_MAX_PATTERN_EDGES 28
+
+/* A pattern: k vertices, n_edges undirected edges (a_i, b_i) stored as
+ * edges[2i], edges[2i+1], 0-based. */
+typedef struct {
+    int32_t k;
+    int32_t n_edges;
+    int32_t edges[2 * GPM_MAX_PATTERN_EDGES];
+} gpm_pattern;
+
+typedef struct {
+    int64_t n;               /* vertices                                    */
+    int64_t m;               /* undirected edges                            */
+    int64_t max_degree;      /* Delta of the symmetric graph (0 if DAG-only) */
+    int64_t max_out_degree;  /* Delta of the degree-oriented DAG             */
+    int64_t device_bytes;    /* device memory held by this graph now         */
+} gpm_graph_meta;
+
+/* Statistics of the last gpm_count / gpm_motifs / gpm_count_batch call. */
+typedef struct {
+    double kernel_ms;        /* sum of the call's kernel times (HIP events)  */
+    double total_ms;         /* host wall time of the call                   */
+    int64_t tasks;           /* root tasks (vertices / edges) issued          */
+    int64_t waves;           /* persistent waves launched                    */
+    int64_t chunk;           /* tasks per queue pop                          */
+    int64_t elements;        /* intersected elements (only when the option
+                                "count_elements" is 1; else -1)               */
+    int64_t list_fetches;    /* neighbour-list reads (same option)            */
+    int64_t frontier_bytes;  /* device frontier buffer size                  */
+    int32_t launches;        /* kernel launches of the call                   */
+    int32_t variant;         /* kernel variant the autotuner chose            */
+} gpm_stats;
+
+/* ---------------------------------------------------------------------- */
+/* context                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t,
+ * may be NULL for the null stream) is where every kernel of the context is
+ * queued; the caller keeps ownership of the stream.  `hbm_budget_bytes`
+ * bounds the device memory the context allocates for frontiers and task
+ * lists (0 = 90% of the free memory at creation).  *out is owned by the
+ * caller and released with gpm_destroy. */
+gpm_status gpm_create(gpm_ctx **out, int device, void *hip_stream,
+                      size_t hbm_budget_bytes);
+
+/* Release every graph, buffer and stream of the context. Waits for pending
+ * device work first.  NULL is accepted. */
+gpm_status gpm_destroy(gpm_ctx *ctx);
+
+/* Message of the last failure on ctx (static storage owned by ctx; valid
+ * until the next call on ctx).  Never NULL. */
+const char *gpm_last_error(const gpm_ctx *ctx);
+
+/* Set a tuning option (for tests and the autotuner's search space):
+ *   "granularity"     0 auto, 1 vertex tasks, 2 edge tasks
+ *   "chunk"           tasks per queue pop (0 = auto)
+ *   "waves_per_cu"    persistent waves per compute unit (0 = auto)
+ *   "setop"           0 auto, 1 binary search, 2 merge path
+ *   "clique_lds"      1 = clique kernel keeps frontiers in LDS (default),
+ *                     0 = force the generic kernel with HBM frontiers
+ *   "rename"          non-clique patterns: 0 ids as given, 1 rename by
+ *                     ascending degree, 2 by descending degree, -1 auto
+ *   "count_elements"  1 = instrumented kernels count intersected elements
+ *                     (slower; never used for timing)
+ *   "autotune"        1 = time candidate configurations on first use of a
+ *                     (graph, pattern) pair and cache the winner
+ * Unknown keys give GPM_E_INVAL. */
+gpm_status gpm_set_option(gpm_ctx *ctx, const char *key, int64_t value);
+
+gpm_status gpm_get_stats(const gpm_ctx *ctx, gpm_stats *out);
+
+/* ---------------------------------------------------------------------- */
+/* graphs (graph loader and preprocessor, Sec. 3)                          */
+/* ---------------------------------------------------------------------- */
+
+/* Load a data graph in CSR form: row_ptr[n+1] (int64, row_ptr[0] = 0,
+ * row_ptr[n] = nnz), col[nnz] (int32).  Lists must be sorted ascending with
+ * no self loops and no duplicates (Table 3's data graphs are symmetric with
+ * no loops or duplicate edges).  With GPM_CSR_SYMMETRIC the graph is the
+ * undirected graph (nnz = 2m); with GPM_CSR_DAG it is an orientation (each
+ * edge once) usable for cliques only.  The arrays are copied (host or, with
+ * GPM_PTRS_DEVICE, device pointers); the caller keeps ownership.  The graph
+ * stays resident until gpm_unload / gpm_destroy.  Preparation (validation,
+ * degree orientation, task lists) runs here or lazily on first use and is
+ * never part of a count's timing, as in the paper's evaluation.
+ * Errors: GPM_E_INVAL (n < 0, nnz < 0, null), GPM_E_CSR, GPM_E_NOMEM. */
+gpm_status gpm_load_csr(gpm_ctx *ctx, int64_t n, int64_t nnz,
+                        const int64_t *row_ptr, const int32_t *col,
+                        uint32_t flags, int32_t *graph_id_out);
+
+gpm_status gpm_unload(gpm_ctx *ctx, int32_t graph_id);
+
+gpm_status gpm_graph_info(gpm_ctx *ctx, int32_t graph_id, gpm_graph_meta *out);
+
+/* ---------------------------------------------------------------------- */
+/* patterns (the paper's generateClique / Pattern(file) API, Sec. 4)       */
+/* ---------------------------------------------------------------------- */
+
+gpm_status gpm_pattern_clique(int k, gpm_pattern *out);
+
+/* Built-in shapes: "edge", "wedge", "triangle", "path4", "star3", "cycle4",
+ * "tailed_triangle", "diamond", "clique4", "clique5" (the 3- and 4-vertex
+ * motifs of Sec. 2.1 plus cliques).  GPM_E_INVAL for an unknown name. */
+gpm_status gpm_pattern_named(const char *name, gpm_pattern *out);
+
+/* Build a pattern from an edge list of n_edges pairs; validates it. */
+gpm_status gpm_pattern_from_edges(int k, int n_edges, const int32_t *edges,
+                                  gpm_pattern *out);
+
+/* The search plan the library uses for a pattern (the paper's pattern
+ * analyzer, Sec. 4): matching order, symmetry order and buffer count.  Host
+ * only; needs no device.  For a clique the plan is the one used on the
+ * degree-oriented DAG (no restrictions: orientation breaks every symmetry). */
+typedef struct {
+    int32_t k;
+    int32_t clique;              /* 1: runs on the oriented DAG              */
+    int32_t aut;                 /* |Aut(P)|                                 */
+    int32_t root_bound;          /* 1: root edges keep one direction (v1<v0),
+                                    the edge-list halving of Sec. 7.2 (2)    */
+    int32_t n_buffers;           /* stored frontier levels X (X <= k-3)      */
+    int32_t n_restrictions;
+    int32_t order[GPM_MAX_K];    /* pattern vertex matched at depth d        */
+    int32_t restrictions[2 * GPM_MAX_PATTERN_EDGES];  /* pairs (a, b):
+                                    v_a > v_b, pattern vertex ids            */
+} gpm_plan_info;
+
+gpm_status gpm_plan(const gpm_pattern *pattern, int mode, gpm_plan_info *out);
+
+/* Adaptive buffering (Sec. 7.2 (3)): waves = min(Y / (X * B * 4 bytes),
+ * tasks, max_resident), at least 1 when X * B * 4 <= Y.  Y = free bytes,
+ * X = stored levels, B = capacity (elements) per level.  Host only.
+ * GPM_E_NOMEM when not even one wave fits. */
+gpm_status gpm_frontier_waves(int64_t free_bytes, int32_t x_levels,
+                              int64_t cap_elems, int64_t n_tasks,
+                              int64_t max_resident, int64_t *waves_out);
+
+/* ---------------------------------------------------------------------- */
+/* counting                                                                */
+/* ---------------------------------------------------------------------- */
+
+/* Exact number of distinct matches of `pattern` in graph `graph_id`
+ * (each subgraph once: completeness and uniqueness, Sec. 2.1), vertex- or
+ * edge-induced (`mode`).  Cliques run on the degree-oriented DAG (Sec. 3,
+ * orientation); other patterns on the symmetric graph with the symmetry
+ * order of Sec. 2.2.  k = 1 returns n, k = 2 returns m, n < k returns 0.
+ * Blocks until the count is on the host (the context's stream is
+ * synchronised).  Errors: GPM_E_PATTERN, GPM_E_UNSUPPORTED, GPM_E_NOMEM,
+ * GPM_E_DEVICE. */
+gpm_status gpm_count(gpm_ctx *ctx, int32_t graph_id, const gpm_pattern *pattern,
+                     int mode, uint64_t *count_out);
+
+/* Vertex-induced counts of every connected k-vertex pattern (k-motif
+ * counting, Sec. 2.1), k = 3 or 4, written to counts_out[len]:
+ *   k = 3 (len >= 2): [wedge, triangle]
+ *   k = 4 (len >= 6): [path4, star3, cycle4, tailed_triangle, diamond, clique4]
+ * Triangle-sharing patterns are computed in one fused kernel and the
+ * 4-cycle separately (multi-pattern kernel fission, Sec. 5.3); the star and
+ * path terms come from degree sums (counting-only pruning, Sec. 5.4 (1)). */
+gpm_status gpm_motifs(gpm_ctx *ctx, int32_t graph_id, int k,
+                      uint64_t *counts_out, size_t len);
+
+/* ---------------------------------------------------------------------- */
+/* batched and served execution                                            */
+/* ---------------------------------------------------------------------- */
+
+enum { GPM_QUERY_COUNT = 0, GPM_QUERY_MOTIFS = 1 };
+
+typedef struct {
+    int32_t graph_id;
+    int32_t kind;            /* GPM_QUERY_COUNT or GPM_QUERY_MOTIFS          */
+    int32_t mode_or_k;       /* COUNT: GPM_*_INDUCED; MOTIFS: 3 or 4          */
+    int32_t reserved;
+    gpm_pattern pattern;     /* COUNT only                                   */
+} gpm_query;
+
+/* Run nq queries in ONE persistent launch whose waves steal chunks of root
+ * tasks from every query through a device-wide queue; outs[6*i ..] receives
+ * query i's result (1 value for COUNT, 2 or 6 for MOTIFS; the rest zero).
+ * outs is a host array of 6*nq uint64 owned by the caller. */
+gpm_status gpm_count_batch(gpm_ctx *ctx, int32_t nq, const gpm_query *queries,
+                           uint64_t *outs);
+
+/* Serving: submit one query without blocking.  The query is admitted when a
+ * launch slot is free and its frontier memory fits the budget; queries
+ * admitted together share one persistent launch, and launches on different
+ * slots overlap on the device.  GPM_E_BUSY when the pending list is full.
+ * *ticket_out identifies the query for gpm_poll / gpm_wait. */
+gpm_status gpm_submit(gpm_ctx *ctx, const gpm_query *query, int64_t *ticket_out);
+
+/* Progress the serving loop; *done_out = 1 when the ticket's result is
+ * ready, in which case counts_out[6] (host, caller-owned) receives it and
+ * the ticket is released. */
+gpm_status gpm_poll(gpm_ctx *ctx, int64_t ticket, int *done_out,
+                    uint64_t *counts_out);
+
+/* Block until the ticket completes or timeout_ns passes (GPM_E_TIMEOUT). */
+gpm_status gpm_wait(gpm_ctx *ctx, int64_t ticket, int64_t timeout_ns,
+                    uint64_t *counts_out);
+
+/* Number of queries submitted but not yet collected. */
+gpm_status gpm_inflight(gpm_ctx *ctx, int64_t *count_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPM_H */

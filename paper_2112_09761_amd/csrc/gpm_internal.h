@@ -1,0 +1,97 @@
+// Internal structures shared by the host runtime and the device kernels of
+// libgpm (never exposed through include/gpm.h).
+#pragma once
+
+#include <cstdint>
+
+namespace gpm {
+
+constexpr int kMaxK = 8;
+constexpr int kWavesPerBlock = 4;       // 256-thread workgroups of four wave64s
+constexpr int kQueues = 8;              // one task queue per XCD
+constexpr int kQueueStride = 16;        // uint64 words between queue counters (128 B)
+constexpr int kResultFields = 8;        // uint64 counters per result slot
+
+// One depth of a search plan (Sec. 2.2: the matching order fixes which
+// earlier pattern vertices a new vertex must be adjacent to -- its candidate
+// set is the intersection of their neighbour lists -- and the symmetry
+// order fixes upper bounds).  Depths 0 and 1 are the root task's vertices.
+struct LevelPlan {
+  uint8_t n_int;           // neighbour lists N(v_j) to intersect, j in int_lv
+  uint8_t n_sub;           // neighbour lists to subtract (vertex-induced mode)
+  int8_t base_buf;         // >= 2: the candidate set starts from the stored
+                           // set of that depth; -1: from the shortest N(v_j)
+  uint8_t flags;           // kLvStore / kLvSlice
+  uint8_t int_lv[kMaxK];
+  uint8_t sub_lv[kMaxK];
+  uint8_t bound_mask;      // bit j: v_depth < v_j
+  uint8_t excl_mask;       // bit j: v_depth != v_j must be checked explicitly
+  uint8_t pad[2];
+};
+
+constexpr uint8_t kLvStore = 1;   // materialise into the depth's frontier buffer
+constexpr uint8_t kLvSlice = 2;   // the set is a bounded prefix of one list;
+                                  // iterate it in place, skipping excl_mask
+
+struct Plan {
+  int32_t k;
+  int32_t root_bound;      // 1: root edges (v0, v1) need v1 < v0
+  int32_t n_store;         // number of stored depths (frontier buffers)
+  int32_t pad;
+  int8_t store_slot[kMaxK];  // depth -> frontier buffer index, -1 if none
+  LevelPlan lv[kMaxK];
+};
+
+enum JobKind : int32_t {
+  kJobClique = 1,      // k-clique on a DAG, frontiers in LDS or HBM
+  kJobDfs = 2,         // generic plan-driven DFS on a symmetric graph
+  kJobEdgeTri = 3,     // per-edge triangle counts and the 4-motif edge terms
+  kJobVertexDeg = 4,   // per-vertex degree terms
+};
+
+constexpr uint32_t kKindClique = 1u << kJobClique;
+constexpr uint32_t kKindDfs = 1u << kJobDfs;
+constexpr uint32_t kKindEdgeTri = 1u << kJobEdgeTri;
+constexpr uint32_t kKindVertexDeg = 1u << kJobVertexDeg;
+constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg;
+
+// One unit of work of a persistent launch: a (graph, pattern plan, range of
+// root tasks) triple with its own result slot.
+struct Job {
+  int32_t kind;
+  int32_t k;               // clique size or plan size
+  int32_t plan;            // index into the launch's plan table (kJobDfs)
+  int32_t slot;            // result slot
+  const int64_t* rp;       // graph view: CSR offsets
+  const int32_t* col;      //             CSR neighbours
+  const int32_t* task_src; // root tasks: edge t is (task_src[t], task_dst[t]);
+  const int32_t* task_dst; //   vertex tasks use vertex t and leave these null
+  int64_t n_tasks;
+  int32_t chunk;           // tasks per queue pop
+  int32_t vertex_tasks;    // 1: tasks are root vertices
+  int32_t cap;             // frontier capacity in elements (max set size)
+  int32_t lds_ok;          // clique job: sets fit the LDS tile
+};
+
+struct KernelArgs {
+  const Job* jobs;
+  const int64_t* job_chunk_begin;  // [n_jobs + 1], prefix of chunks per job
+  int32_t n_jobs;
+  int32_t lds_cap;                 // clique LDS tile (elements per set)
+  const Plan* plans;
+  const int64_t* queue_begin;      // [kQueues + 1] chunk ranges of the queues
+  unsigned long long* queue_cnt;   // [kQueues * kQueueStride]
+  unsigned long long* results;     // [slots * kResultFields]
+  unsigned long long* counters;    // [4]: elements, list fetches (instrumented)
+  int32_t* fbuf;                   // HBM frontier buffers
+  int64_t wave_stride;             // int32 words of fbuf per wave
+  int32_t lds_words;               // int32 words of dynamic LDS per wave
+  int32_t pad;
+};
+
+// Host-side launcher (kernels.hip).  Returns a hipError_t as int.
+int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a,
+                      int blocks, size_t lds_bytes, void* stream);
+int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
+
+}  // namespace gpm

@@ -1,0 +1,628 @@
+// Device code of libgpm: pattern-aware DFS subgraph extension on gfx950.
+//
+// One persistent launch consumes chunks of root tasks from per-XCD queues
+// (work stealing across XCDs when a queue runs dry).  Each task is walked by
+// one wave64: all 64 lanes follow the same depth-first walk and share every
+// set operation (the paper's warp-centric two-level parallelism, Sec. 5.1,
+// mapped to 64-wide wavefronts).  Set intersection / difference / bounding
+// (Sec. 6.1) evaluate one element per lane, test membership by binary search
+// and compact the survivors with ballot + mbcnt + popcount.  Exact uint64
+// counts stay in per-lane registers and are reduced once per job.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "gpm_internal.h"
+
+namespace gpm {
+
+// ---------------------------------------------------------------------------
+// wave-level helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int32_t uni(int32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m in lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int32_t y = __shfl_up(x, off, 64);
+    if (l >= off) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;  // valid in lane 0
+}
+
+// Cross-lane visibility of a wave's own stores before other lanes read them.
+__device__ __forceinline__ void wave_sync_mem() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First index i in [0, n) with a[i] >= key (n if none).  Branch-free body:
+// the iteration count depends only on n.
+template <typename T>
+__device__ __forceinline__ int32_t lower_bound(const T* a, int32_t n, int32_t key) {
+  if (n <= 0) return 0;
+  int32_t base = 0;
+  while (n > 1) {
+    int32_t half = n >> 1;
+    base = (a[base + half] < key) ? base + half : base;
+    n -= half;
+  }
+  return base + (a[base] < key ? 1 : 0);
+}
+
+template <typename T>
+__device__ __forceinline__ bool member(const T* a, int32_t n, int32_t key) {
+  int32_t p = lower_bound(a, n, key);
+  return p < n && a[p] == key;
+}
+
+// First index i in [0, n) with a[i] > key.
+template <typename T>
+__device__ __forceinline__ int32_t upper_bound(const T* a, int32_t n, int32_t key) {
+  if (n <= 0) return 0;
+  int32_t base = 0;
+  while (n > 1) {
+    int32_t half = n >> 1;
+    base = (a[base + half] <= key) ? base + half : base;
+    n -= half;
+  }
+  return base + (a[base] <= key ? 1 : 0);
+}
+
+struct ElemCounter {
+  uint64_t elems = 0;
+  uint64_t fetches = 0;
+};
+
+// ---------------------------------------------------------------------------
+// set operations (Sec. 6.1): one element of the iterated list per lane
+// ---------------------------------------------------------------------------
+
+// out = A ∩ B (A iterated, B probed), order of A kept; returns |out|.
+template <typename TA, typename TB, typename TO>
+__device__ __forceinline__ int32_t intersect_store(const TA* A, int32_t na, const TB* B,
+                                                   int32_t nb, TO* out) {
+  int32_t total = 0;
+  const int l = lane_id();
+  for (int32_t ib = 0; ib < na; ib += 64) {
+    int32_t i = ib + l;
+    bool keep = false;
+    int32_t x = 0;
+    if (i < na) {
+      x = A[i];
+      keep = member(B, nb, x);
+    }
+    uint64_t m = wave_ballot(keep);
+    if (keep) out[total + (int32_t)lanes_below(m)] = x;
+    total += (int32_t)__popcll(m);
+  }
+  wave_sync_mem();
+  return total;
+}
+
+// |A ∩ B| contributed by this lane.
+template <typename TA, typename TB>
+__device__ __forceinline__ uint32_t intersect_count(const TA* A, int32_t na, const TB* B,
+                                                    int32_t nb) {
+  uint32_t c = 0;
+  const int l = lane_id();
+  for (int32_t i = l; i < na; i += 64) c += member(B, nb, (int32_t)A[i]) ? 1u : 0u;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// k-clique on the oriented DAG (Sec. 3 orientation; Alg. 1 with every level
+// an intersection).  Sets F_d of candidates for v_d; the last two vertices
+// are counted together as the number of DAG edges inside F_{k-2}.
+// ---------------------------------------------------------------------------
+
+// Sum over w in F of |F ∩ N+(w)|.  P is scratch of s + 1 ints.
+template <bool CE, typename TF, typename TP>
+__device__ __forceinline__ uint32_t clique_leaf(const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col,
+                                                const TF* F, int32_t s, TP* P,
+                                                ElemCounter& ec) {
+  const int l = lane_id();
+  int32_t running = 0;
+  for (int32_t ib = 0; ib < s; ib += 64) {
+    int32_t i = ib + l;
+    int32_t d = 0;
+    if (i < s) {
+      int32_t w = F[i];
+      d = (int32_t)(rp[w + 1] - rp[w]);
+    }
+    int32_t inc = wave_incl_scan(d);
+    if (i < s) P[i + 1] = running + inc;
+    running += __shfl(inc, 63, 64);
+  }
+  if (l == 0) P[0] = 0;
+  wave_sync_mem();
+  running = uni(running);
+  if (CE) {
+    ec.elems += (uint64_t)s * (uint64_t)s + (uint64_t)running;
+    ec.fetches += (uint64_t)s;
+  }
+  uint32_t c = 0;
+  for (int32_t tb = 0; tb < running; tb += 64) {
+    int32_t t = tb + l;
+    if (t < running) {
+      // owner i: P[i] <= t < P[i+1]
+      int32_t i = upper_bound(P + 1, s, t);
+      int32_t w = F[i];
+      int32_t x = col[rp[w] + (t - P[i])];
+      c += member(F, s, x) ? 1u : 0u;
+    }
+  }
+  return c;
+}
+
+// Count k-cliques (k >= 3) whose first two vertices are the DAG edge u->v.
+// U = N+(u) (LDS-staged or global), bufs: (k-3) sets of cap ints, P: cap+1,
+// st: 2*kMaxK ints of wave state.
+template <bool CE, typename TU, typename TB>
+__device__ __forceinline__ uint32_t clique_edge(const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col, int k,
+                                                const TU* U, int32_t du, int32_t v,
+                                                TB* bufs, TB* P, int32_t cap,
+                                                int32_t* st, ElemCounter& ec) {
+  const int32_t* Nv = col + rp[v];
+  const int32_t dv = uni((int32_t)(rp[v + 1] - rp[v]));
+  if (CE) {
+    ec.elems += (uint64_t)du + (uint64_t)dv;
+    ec.fetches += 2;
+  }
+  if (k == 3) return intersect_count(Nv, dv, U, du);
+  TB* F2 = bufs;
+  int32_t s2 = uni(intersect_store(Nv, dv, U, du, F2));
+  if (s2 < k - 2) return 0;
+  if (k == 4) return clique_leaf<CE>(rp, col, F2, s2, P, ec);
+
+  // depths 2 .. k-3 are iterated; F_{k-2} goes to the leaf
+  uint32_t c = 0;
+  int32_t* sz = st;
+  int32_t* ix = st + kMaxK;
+  int d = 2;
+  if (lane_id() == 0) { sz[2] = s2; ix[2] = 0; }
+  wave_sync_mem();
+  for (;;) {
+    int32_t i = uni(ix[d]);
+    int32_t s = uni(sz[d]);
+    if (i >= s) {
+      if (d == 2) break;
+      --d;
+      if (lane_id() == 0) ix[d] = ix[d] + 1;
+      wave_sync_mem();
+      continue;
+    }
+    TB* Fd = bufs + (size_t)(d - 2) * cap;
+    TB* Fn = Fd + cap;
+    int32_t w = uni(Fd[i]);
+    const int32_t* Nw = col + rp[w];
+    int32_t dw = uni((int32_t)(rp[w + 1] - rp[w]));
+    int32_t sn;
+    // iterate the shorter side; probe LDS-resident F when N+(w) is not much longer
+    if (dw <= 4 * s) sn = uni(intersect_store(Nw, dw, Fd, s, Fn));
+    else sn = uni(intersect_store(Fd, s, Nw, dw, Fn));
+    if (CE) {
+      ec.elems += (uint64_t)s + (uint64_t)dw;
+      ec.fetches += 1;
+    }
+    if (d + 1 == k - 2) {
+      if (sn >= 2) c += clique_leaf<CE>(rp, col, Fn, sn, P, ec);
+      if (lane_id() == 0) ix[d] = i + 1;
+      wave_sync_mem();
+      continue;
+    }
+    if (sn < k - (d + 1)) {
+      if (lane_id() == 0) ix[d] = i + 1;
+      wave_sync_mem();
+      continue;
+    }
+    ++d;
+    if (lane_id() == 0) { sz[d] = sn; ix[d] = 0; }
+    wave_sync_mem();
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// generic plan-driven DFS (Alg. 1 generalised by the plan table)
+// ---------------------------------------------------------------------------
+
+struct DfsState {
+  int32_t v[kMaxK];        // matched data vertices by depth
+  int32_t sz[kMaxK];       // candidate set size by depth
+  int32_t ix[kMaxK];       // iteration index by depth
+  int32_t pad;
+  const int32_t* set[kMaxK];  // candidate set elements by depth
+};
+
+// Candidate set of depth `d` (Sec. 2.2 connectivity constraints + symmetry
+// bounds; in vertex-induced mode also the non-adjacency constraints).
+// STORE: materialise into `out` and return its (uniform) size.
+// !STORE: return this lane's share of the set size (count-only leaf).
+// Slice levels return the bounded base length and point st.set[d] at it.
+template <bool STORE, bool CE>
+__device__ __forceinline__ int32_t dfs_level(const int64_t* __restrict__ rp,
+                                             const int32_t* __restrict__ col,
+                                             const LevelPlan& L, DfsState& st, int d,
+                                             int32_t* out, ElemCounter& ec) {
+  int32_t bound = INT_MAX;
+  for (int j = 0; j < d; ++j)
+    if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
+
+  const int32_t* base;
+  int32_t blen;
+  int base_i = -1;
+  if (L.base_buf >= 0) {
+    base = st.set[L.base_buf];
+    blen = st.sz[L.base_buf];
+  } else {
+    blen = INT_MAX;
+    base = nullptr;
+    for (int i = 0; i < L.n_int; ++i) {
+      int32_t vj = st.v[L.int_lv[i]];
+      int32_t len = (int32_t)(rp[vj + 1] - rp[vj]);
+      if (len < blen) { blen = len; base_i = i; base = col + rp[vj]; }
+    }
+  }
+  blen = uni(lower_bound(base, uni(blen), bound));
+  const int n_probe = L.n_int - (base_i >= 0 ? 1 : 0);
+
+  if (CE) {
+    uint64_t e = (uint64_t)blen;
+    for (int i = 0; i < L.n_int; ++i) {
+      if (i == base_i) continue;
+      int32_t vj = st.v[L.int_lv[i]];
+      e += (uint64_t)(rp[vj + 1] - rp[vj]);
+    }
+    for (int i = 0; i < L.n_sub; ++i) {
+      int32_t vj = st.v[L.sub_lv[i]];
+      e += (uint64_t)(rp[vj + 1] - rp[vj]);
+    }
+    ec.elems += e;
+    ec.fetches += 1 + n_probe + L.n_sub;
+  }
+
+  if (L.flags & kLvSlice) {
+    st.set[d] = base;
+    return blen;
+  }
+
+  if (!STORE && n_probe == 0 && L.n_sub == 0) {
+    // size-only leaf: |bounded base| minus the excluded matched vertices in it
+    if (lane_id() != 0) return 0;
+    int32_t c = blen;
+    for (int j = 0; j < d; ++j)
+      if ((L.excl_mask >> j) & 1)
+        if (st.v[j] < bound && member(base, blen, st.v[j])) --c;
+    return c;
+  }
+
+  const int l = lane_id();
+  int32_t total = 0;
+  for (int32_t ib = 0; ib < blen; ib += 64) {
+    int32_t i = ib + l;
+    bool keep = i < blen;
+    int32_t x = keep ? base[i] : 0;
+    for (int q = 0; q < L.n_int && keep; ++q) {
+      if (q == base_i) continue;
+      int32_t vj = st.v[L.int_lv[q]];
+      const int32_t* N = col + rp[vj];
+      keep = member(N, (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int q = 0; q < L.n_sub && keep; ++q) {
+      int32_t vj = st.v[L.sub_lv[q]];
+      const int32_t* N = col + rp[vj];
+      keep = !member(N, (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int j = 0; j < d && keep; ++j)
+      if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
+    if (STORE) {
+      uint64_t m = wave_ballot(keep);
+      if (keep) out[total + (int32_t)lanes_below(m)] = x;
+      total += (int32_t)__popcll(m);
+    } else {
+      total += keep ? 1 : 0;
+    }
+  }
+  if (STORE) {
+    wave_sync_mem();
+    st.set[d] = out;
+  }
+  return total;
+}
+
+__device__ __forceinline__ bool slice_excluded(const LevelPlan& L, const DfsState& st,
+                                               int d, int32_t x) {
+  for (int j = 0; j < d; ++j)
+    if (((L.excl_mask >> j) & 1) && st.v[j] == x) return true;
+  return false;
+}
+
+// All matches extending the root (v0, v1): the depth-first walk over depths
+// 2 .. k-1; depth k-1 is count-only.  Wave-uniform control flow throughout.
+template <bool CE>
+__device__ uint32_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const Plan& P, int32_t v0, int32_t v1, int32_t* fb,
+                             int32_t cap, DfsState& st, ElemCounter& ec) {
+  const int k = P.k;
+  st.v[0] = v0;
+  st.v[1] = v1;
+  if (k == 3) return (uint32_t)dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, ec);
+  uint32_t c = 0;
+  int d = 2;
+  {
+    int32_t* out = fb + (size_t)(P.store_slot[2] < 0 ? 0 : P.store_slot[2]) * cap;
+    st.sz[2] = uni(dfs_level<true, CE>(rp, col, P.lv[2], st, 2, out, ec));
+    st.ix[2] = 0;
+  }
+  for (;;) {
+    if (st.ix[d] >= st.sz[d]) {
+      if (d == 2) break;
+      --d;
+      ++st.ix[d];
+      continue;
+    }
+    int32_t x = uni(st.set[d][st.ix[d]]);
+    if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) {
+      ++st.ix[d];
+      continue;
+    }
+    st.v[d] = x;
+    if (d + 1 == k - 1) {
+      c += (uint32_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, ec);
+      ++st.ix[d];
+      continue;
+    }
+    ++d;
+    int32_t* out = fb + (size_t)(P.store_slot[d] < 0 ? 0 : P.store_slot[d]) * cap;
+    st.sz[d] = uni(dfs_level<true, CE>(rp, col, P.lv[d], st, d, out, ec));
+    st.ix[d] = 0;
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// the persistent kernel
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t pop_chunk(unsigned long long* qcnt, const int64_t* qbeg,
+                                             int home, uint32_t& dead) {
+  for (int i = 0; i < kQueues; ++i) {
+    int x = (home + i) & (kQueues - 1);
+    if ((dead >> x) & 1u) continue;
+    int64_t limit = qbeg[x + 1] - qbeg[x];
+    unsigned long long c = 0;
+    if (lane_id() == 0) c = atomicAdd(&qcnt[x * kQueueStride], 1ull);
+    c = __shfl(c, 0, 64);
+    if ((int64_t)c < limit) return qbeg[x] + (int64_t)c;
+    dead |= 1u << x;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int find_job(const int64_t* jbeg, int n_jobs, int64_t c) {
+  int lo = 0, hi = n_jobs;  // jbeg[lo] <= c < jbeg[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (jbeg[mid] <= c) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void flush(unsigned long long* results, int slot, uint64_t* acc,
+                                      int nf) {
+  for (int f = 0; f < nf; ++f) {
+    uint64_t s = wave_sum_u64(acc[f]);
+    if (lane_id() == 0 && s) atomicAdd(&results[(size_t)slot * kResultFields + f], s);
+    acc[f] = 0;
+  }
+}
+
+template <uint32_t KINDS, bool CE>
+__global__ void __launch_bounds__(kWavesPerBlock * 64)
+gpm_persistent(KernelArgs a) {
+  extern __shared__ int32_t lds[];
+  __shared__ int32_t lds_state[kWavesPerBlock][2 * kMaxK];
+  const int w = threadIdx.x >> 6;
+  int32_t* my = lds + (size_t)w * a.lds_words;
+  int32_t* st_words = lds_state[w];
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  int32_t* fb = a.fbuf ? a.fbuf + gw * a.wave_stride : nullptr;
+  const int home = (int)(blockIdx.x & (kQueues - 1));  // blocks are dealt round-robin to XCDs
+  uint32_t dead = 0;
+  int cur = -1;
+  int cur_slot = 0;
+  int nf = 0;
+  uint64_t acc[4] = {0, 0, 0, 0};
+  ElemCounter ec;
+  int32_t cached_u = -1;
+  DfsState st;
+
+  for (;;) {
+    int64_t c = pop_chunk(a.queue_cnt, a.queue_begin, home, dead);
+    if (c < 0) break;
+    int j = uni(find_job(a.job_chunk_begin, a.n_jobs, c));
+    if (j != cur) {
+      if (cur >= 0) flush(a.results, cur_slot, acc, nf);
+      cur = j;
+      cached_u = -1;
+    }
+    const Job& J = a.jobs[j];
+    const int kind = J.kind;
+    cur_slot = J.slot;
+    const int64_t t0 = (c - a.job_chunk_begin[j]) * (int64_t)J.chunk;
+    const int64_t t1 = min(t0 + (int64_t)J.chunk, J.n_tasks);
+    const int64_t* __restrict__ rp = J.rp;
+    const int32_t* __restrict__ col = J.col;
+
+    if ((KINDS & kKindClique) && kind == kJobClique) {
+      nf = 1;
+      const int k = J.k;
+      for (int64_t t = t0; t < t1; ++t) {
+        int32_t u = uni(J.task_src[t]);
+        int32_t v = uni(J.task_dst[t]);
+        int32_t du = uni((int32_t)(rp[u + 1] - rp[u]));
+        if (J.lds_ok && du <= a.lds_cap) {
+          // LDS tile: U | F_2 .. F_{k-2} | P
+          int32_t* U = my;
+          int32_t* bufs = my + a.lds_cap;
+          int32_t* P = bufs + (size_t)(k - 3 > 0 ? k - 3 : 0) * a.lds_cap;
+          if (u != cached_u) {
+            const int32_t* Nu = col + rp[u];
+            for (int32_t i = lane_id(); i < du; i += 64) U[i] = Nu[i];
+            wave_sync_mem();
+            cached_u = u;
+          }
+          acc[0] += clique_edge<CE>(rp, col, k, (const int32_t*)U, du, v, bufs, P, a.lds_cap,
+                                    st_words, ec);
+        } else {
+          const int32_t* U = col + rp[u];
+          int32_t* bufs = fb;
+          int32_t* P = fb + (size_t)(k - 3 > 0 ? k - 3 : 0) * J.cap;
+          acc[0] += clique_edge<CE>(rp, col, k, U, du, v, bufs, P, J.cap, st_words, ec);
+        }
+      }
+    } else if ((KINDS & kKindDfs) && kind == kJobDfs) {
+      nf = 1;
+      const Plan& P = a.plans[J.plan];
+      for (int64_t t = t0; t < t1; ++t) {
+        if (J.vertex_tasks) {
+          int32_t v0 = (int32_t)t;
+          const int32_t* N0 = col + rp[v0];
+          int32_t d0 = uni((int32_t)(rp[v0 + 1] - rp[v0]));
+          int32_t end = P.root_bound ? uni(lower_bound(N0, d0, v0)) : d0;
+          for (int32_t e = 0; e < end; ++e) {
+            int32_t v1 = uni(N0[e]);
+            acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, st, ec);
+          }
+        } else {
+          int32_t v0 = uni(J.task_src[t]);
+          int32_t v1 = uni(J.task_dst[t]);
+          acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, st, ec);
+        }
+      }
+    } else if ((KINDS & kKindEdgeTri) && kind == kJobEdgeTri) {
+      // per undirected edge e = (u, v), u > v: t_e = |N(u) ∩ N(v)|
+      // f0 += t_e (3T in total), f1 += C(t_e, 2) (non-induced diamonds,
+      // Alg. 3), f2 += t_e (d_u + d_v - 4) (twice the non-induced tailed
+      // triangles), f3 += (d_u - 1)(d_v - 1) (4-paths through e as middle edge
+      // plus 3 per triangle)
+      nf = 4;
+      for (int64_t t = t0; t < t1; ++t) {
+        int32_t u = uni(J.task_src[t]);
+        int32_t v = uni(J.task_dst[t]);
+        int32_t du = uni((int32_t)(rp[u + 1] - rp[u]));
+        int32_t dv = uni((int32_t)(rp[v + 1] - rp[v]));
+        const int32_t* Nu = col + rp[u];
+        const int32_t* Nv = col + rp[v];
+        uint32_t part = (du <= dv) ? intersect_count(Nu, du, Nv, dv)
+                                   : intersect_count(Nv, dv, Nu, du);
+        if (CE) {
+          ec.elems += (uint64_t)du + (uint64_t)dv;
+          ec.fetches += 2;
+        }
+        uint64_t te = wave_sum_u64(part);
+        te = (uint64_t)__shfl((unsigned long long)te, 0, 64);
+        if (lane_id() == 0) {
+          acc[0] += te;
+          acc[1] += te * (te - (te ? 1 : 0)) / 2;
+          acc[2] += te * (uint64_t)((int64_t)du + dv - 4);
+          acc[3] += (uint64_t)(du - 1) * (uint64_t)(dv - 1);
+        }
+      }
+    } else if ((KINDS & kKindVertexDeg) && kind == kJobVertexDeg) {
+      // f0 += C(d, 2), f1 += C(d, 3) over the chunk's vertices
+      nf = 2;
+      for (int64_t t = t0 + lane_id(); t < t1; t += 64) {
+        uint64_t d = (uint64_t)(rp[t + 1] - rp[t]);
+        if (d >= 2) acc[0] += d * (d - 1) / 2;
+        if (d >= 3) acc[1] += (uint64_t)((unsigned __int128)d * (d - 1) * (d - 2) / 6);
+      }
+    }
+  }
+  if (cur >= 0) flush(a.results, cur_slot, acc, nf);
+  if (CE) {
+    uint64_t e = wave_sum_u64(ec.elems);
+    uint64_t f = wave_sum_u64(ec.fetches);
+    if (lane_id() == 0) {
+      atomicAdd(&a.counters[0], (unsigned long long)e / 64ull);
+      atomicAdd(&a.counters[1], (unsigned long long)f / 64ull);
+    }
+  }
+}
+
+__global__ void fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+template <uint32_t KINDS, bool CE>
+static hipError_t launch_t(const KernelArgs& a, int blocks, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((gpm_persistent<KINDS, CE>), dim3(blocks), dim3(kWavesPerBlock * 64),
+                     lds, s, a);
+  return hipGetLastError();
+}
+
+template <bool CE>
+static hipError_t launch_kinds(uint32_t kinds, const KernelArgs& a, int blocks, size_t lds,
+                               hipStream_t s) {
+  switch (kinds) {
+    case kKindClique: return launch_t<kKindClique, CE>(a, blocks, lds, s);
+    case kKindDfs: return launch_t<kKindDfs, CE>(a, blocks, lds, s);
+    case kKindEdgeTri: return launch_t<kKindEdgeTri, CE>(a, blocks, lds, s);
+    case kKindVertexDeg: return launch_t<kKindVertexDeg, CE>(a, blocks, lds, s);
+    default: return launch_t<kKindAll, CE>(a, blocks, lds, s);
+  }
+}
+
+int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a, int blocks,
+                      size_t lds_bytes, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = count_elems ? launch_kinds<true>(kinds, a, blocks, lds_bytes, s)
+                             : launch_kinds<false>(kinds, a, blocks, lds_bytes, s);
+  return (int)e;
+}
+
+int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream) {
+  if (n <= 0) return 0;
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(fill_u64, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, n,
+                     v);
+  return (int)hipGetLastError();
+}
+
+}  // namespace gpm

@@ -1,0 +1,1236 @@
+// Host runtime of libgpm: the C ABI of include/gpm.h.
+//
+// Graph loader and preprocessor (Sec. 3): validation, degree orientation for
+// cliques, root task lists (edge list halved when the plan orders v1 < v0,
+// Sec. 7.2 (2)).  Runtime (Sec. 7): frontier buffers sized to the device
+// memory budget (adaptive buffering, Sec. 7.2 (3)), persistent launches fed
+// by per-XCD chunk queues (the chunked scheduling idea of Sec. 7.1 on one
+// GPU), batched launches over many queries, and a serving loop that admits
+// queries by frontier memory and overlaps launches on several streams.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gpm.h"
+#include "gpm_internal.h"
+#include "plan.h"
+
+using namespace gpm;
+
+namespace {
+
+constexpr int kMaxSlots = 4;
+
+struct HostCSR {
+  int64_t n = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> col;
+};
+
+struct GraphView {
+  int64_t n = 0, nnz = 0;
+  int64_t* rp = nullptr;
+  int32_t* col = nullptr;
+  int32_t* src = nullptr;  // row of every CSR position (root edge tasks)
+  int64_t max_deg = 0;
+};
+
+struct Graph {
+  bool dag_only = false;
+  HostCSR host;             // symmetric graph, or the given DAG when dag_only
+  GraphView sym;            // symmetric graph on device (unless dag_only)
+  GraphView dag;            // degree-oriented DAG (lazy) or the given DAG
+  bool dag_ready = false;
+  int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
+  int32_t* lo_dst = nullptr;
+  int64_t n_lo = 0;
+  bool lo_ready = false;
+  int64_t m = 0;
+  size_t bytes = 0;
+};
+
+struct QueryWork {
+  // jobs of one query and how to combine their slots into results
+  int kind = GPM_QUERY_COUNT;
+  int k = 0;
+  int first_job = 0, n_jobs = 0;
+  uint64_t constant = 0;   // result known on the host (k <= 2, n < k, ...)
+  bool has_constant = false;
+  int64_t ticket = -1;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void* d_meta = nullptr;  size_t d_meta_bytes = 0;    // jobs, plans, offsets
+  unsigned long long* d_res = nullptr; size_t d_res_words = 0;  // results + queues + counters
+  int32_t* d_fbuf = nullptr; size_t d_fbuf_bytes = 0;
+  void* h_stage = nullptr; size_t h_stage_bytes = 0;    // pinned
+  unsigned long long* h_res = nullptr; size_t h_res_words = 0;  // pinned
+  bool busy = false;
+  size_t frontier_bytes_in_use = 0;
+  std::vector<QueryWork> queries;
+  int n_jobs = 0;
+  int n_launch = 0;
+  size_t counters_off = 0;   // word offset of the instrumentation counters in h_res
+  std::chrono::steady_clock::time_point t_start;
+};
+
+struct Pending {
+  gpm_query q;
+  int64_t ticket;
+};
+
+}  // namespace
+
+struct gpm_ctx {
+  int device = 0;
+  hipStream_t user_stream = nullptr;
+  size_t budget = 0;
+  int cus = 256;
+  std::string err;
+  std::map<int32_t, std::unique_ptr<Graph>> graphs;
+  int32_t next_graph = 1;
+  // options
+  int64_t opt_granularity = 0, opt_chunk = 0, opt_waves_per_cu = 0, opt_setop = 0;
+  int64_t opt_clique_lds = 1, opt_rename = 0, opt_count_elements = 0, opt_autotune = 0;
+  int64_t opt_lds_tile = 0, opt_max_batch = 4096, opt_serve_slots = kMaxSlots;
+  int64_t opt_max_pending = 1 << 20;
+  gpm_stats stats{};
+  Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
+  // serving
+  std::deque<Pending> pending;
+  std::unordered_map<int64_t, std::array<uint64_t, 6>> done;
+  int64_t next_ticket = 1;
+  size_t serve_frontier_in_use = 0;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+static gpm_status fail(gpm_ctx* c, gpm_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIP_TRY(c, expr)                                                            \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail((c), GPM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+static gpm_status dev_upload(gpm_ctx* c, T** dst, const T* src, size_t count) {
+  *dst = nullptr;
+  if (count == 0) count = 1;
+  HIP_TRY(c, hipMalloc((void**)dst, count * sizeof(T)));
+  if (src) HIP_TRY(c, hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return GPM_OK;
+}
+
+static void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static void free_view(GraphView& v) {
+  dev_free(v.rp);
+  dev_free(v.col);
+  dev_free(v.src);
+  v = GraphView{};
+}
+
+static void free_graph(Graph& g) {
+  free_view(g.sym);
+  free_view(g.dag);
+  dev_free(g.lo_src);
+  dev_free(g.lo_dst);
+  g.lo_src = g.lo_dst = nullptr;
+}
+
+static int64_t max_degree(const HostCSR& h) {
+  int64_t m = 0;
+  for (int64_t u = 0; u < h.n; ++u) m = std::max(m, h.rp[u + 1] - h.rp[u]);
+  return m;
+}
+
+static gpm_status upload_view(gpm_ctx* c, const HostCSR& h, bool with_src, GraphView* v,
+                              size_t* bytes) {
+  v->n = h.n;
+  v->nnz = h.rp[h.n];
+  v->max_deg = max_degree(h);
+  gpm_status st = dev_upload(c, &v->rp, h.rp.data(), h.rp.size());
+  if (st) return st;
+  st = dev_upload(c, &v->col, h.col.data(), h.col.size());
+  if (st) return st;
+  *bytes += h.rp.size() * 8 + h.col.size() * 4;
+  if (with_src) {
+    std::vector<int32_t> src(h.col.size());
+    for (int64_t u = 0; u < h.n; ++u)
+      for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) src[p] = (int32_t)u;
+    st = dev_upload(c, &v->src, src.data(), src.size());
+    if (st) return st;
+    *bytes += src.size() * 4;
+  }
+  return GPM_OK;
+}
+
+// Orientation by (degree, id) (Sec. 3 "Graph Loader and Preprocessor":
+// orientation halves the edges and shrinks the maximum degree).
+static HostCSR orient_by_degree(const HostCSR& g) {
+  HostCSR d;
+  d.n = g.n;
+  d.rp.assign(g.n + 1, 0);
+  auto before = [&](int64_t u, int64_t v) {
+    int64_t du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];
+    return du < dv || (du == dv && u < v);
+  };
+  for (int64_t u = 0; u < g.n; ++u) {
+    int64_t c = 0;
+    for (int64_t p = g.rp[u]; p < g.rp[u + 1]; ++p) c += before(u, g.col[p]);
+    d.rp[u + 1] = d.rp[u] + c;
+  }
+  d.col.resize(d.rp[g.n]);
+  for (int64_t u = 0; u < g.n; ++u) {
+    int64_t o = d.rp[u];
+    for (int64_t p = g.rp[u]; p < g.rp[u + 1]; ++p)
+      if (before(u, g.col[p])) d.col[o++] = g.col[p];
+  }
+  return d;
+}
+
+static gpm_status ensure_dag(gpm_ctx* c, Graph& g) {
+  if (g.dag_ready) return GPM_OK;
+  if (g.dag_only) {
+    gpm_status st = upload_view(c, g.host, true, &g.dag, &g.bytes);
+    if (st) return st;
+  } else {
+    HostCSR d = orient_by_degree(g.host);
+    gpm_status st = upload_view(c, d, true, &g.dag, &g.bytes);
+    if (st) return st;
+  }
+  g.dag_ready = true;
+  return GPM_OK;
+}
+
+// Root edges (v0, v1) with v1 < v0: one direction per undirected edge.
+static gpm_status ensure_lower(gpm_ctx* c, Graph& g) {
+  if (g.lo_ready) return GPM_OK;
+  std::vector<int32_t> s, d;
+  s.reserve(g.m);
+  d.reserve(g.m);
+  for (int64_t u = 0; u < g.host.n; ++u)
+    for (int64_t p = g.host.rp[u]; p < g.host.rp[u + 1] && g.host.col[p] < u; ++p) {
+      s.push_back((int32_t)u);
+      d.push_back(g.host.col[p]);
+    }
+  g.n_lo = (int64_t)s.size();
+  gpm_status st = dev_upload(c, &g.lo_src, s.data(), s.size());
+  if (st) return st;
+  st = dev_upload(c, &g.lo_dst, d.data(), d.size());
+  if (st) return st;
+  g.bytes += s.size() * 8;
+  g.lo_ready = true;
+  return GPM_OK;
+}
+
+static Graph* find_graph(gpm_ctx* c, int32_t id) {
+  auto it = c->graphs.find(id);
+  return it == c->graphs.end() ? nullptr : it->second.get();
+}
+
+// ---------------------------------------------------------------------------
+// job construction
+// ---------------------------------------------------------------------------
+
+struct JobPlanSet {
+  std::vector<Job> jobs;
+  std::vector<Plan> plans;
+  std::vector<int64_t> need_words;  // per job: HBM frontier words per wave
+};
+
+static int default_chunk(const gpm_ctx* c, int kind) {
+  if (c->opt_chunk > 0 && kind != kJobVertexDeg) return (int)c->opt_chunk;
+  switch (kind) {
+    case kJobVertexDeg: return 4096;
+    case kJobEdgeTri: return 32;
+    default: return 8;
+  }
+}
+
+static int lds_tile(const gpm_ctx* c) {
+  return c->opt_lds_tile > 0 ? (int)c->opt_lds_tile : 512;
+}
+
+// Append the jobs counting `p` in `mode` on graph g; *constant set when the
+// answer needs no kernel.
+static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int mode,
+                                 JobPlanSet& js, QueryWork& qw) {
+  std::string err;
+  gpm_status st = validate_pattern(p, &err);
+  if (st) return fail(c, st, err);
+  bool clique = is_clique(p);
+  if (g.dag_only && !clique)
+    return fail(c, GPM_E_UNSUPPORTED, "non-clique pattern on a DAG-only graph");
+  const int64_t n = g.host.n;
+  qw.k = p.k;
+  if (p.k == 1) { qw.has_constant = true; qw.constant = (uint64_t)n; return GPM_OK; }
+  if (p.k == 2) { qw.has_constant = true; qw.constant = (uint64_t)g.m; return GPM_OK; }
+  if (n < p.k || g.m == 0) { qw.has_constant = true; qw.constant = 0; return GPM_OK; }
+
+  if (clique) {
+    st = ensure_dag(c, g);
+    if (st) return st;
+    const int64_t cap = std::max<int64_t>(g.dag.max_deg, 1);
+    if (p.k - 2 > cap) { qw.has_constant = true; qw.constant = 0; return GPM_OK; }
+    Job J{};
+    J.rp = g.dag.rp;
+    J.col = g.dag.col;
+    J.task_src = g.dag.src;
+    J.task_dst = g.dag.col;
+    J.n_tasks = g.dag.nnz;
+    J.k = p.k;
+    J.cap = (int32_t)cap;
+    if (c->opt_clique_lds) {
+      J.kind = kJobClique;
+      J.chunk = default_chunk(c, kJobClique);
+      J.lds_ok = 1;
+      js.jobs.push_back(J);
+      js.need_words.push_back(0);  // HBM fallback sized at launch, once the LDS tile is known
+    } else {
+      HostPlan hp;
+      st = build_plan(p, mode, true, &hp, &err);
+      if (st) return fail(c, st, err);
+      J.kind = kJobDfs;
+      J.chunk = default_chunk(c, kJobDfs);
+      J.plan = (int32_t)js.plans.size();
+      js.plans.push_back(hp.plan);
+      js.jobs.push_back(J);
+      js.need_words.push_back((int64_t)hp.n_buffers * cap);
+    }
+    qw.n_jobs += 1;
+    return GPM_OK;
+  }
+
+  HostPlan hp;
+  st = build_plan(p, mode, false, &hp, &err);
+  if (st) return fail(c, st, err);
+  const int64_t cap = std::max<int64_t>(g.sym.max_deg, 1);
+  Job J{};
+  J.kind = kJobDfs;
+  J.k = p.k;
+  J.rp = g.sym.rp;
+  J.col = g.sym.col;
+  J.cap = (int32_t)cap;
+  J.chunk = default_chunk(c, kJobDfs);
+  J.plan = (int32_t)js.plans.size();
+  bool vertex = c->opt_granularity == 1;
+  if (vertex) {
+    J.vertex_tasks = 1;
+    J.n_tasks = n;
+  } else if (hp.plan.root_bound) {
+    st = ensure_lower(c, g);
+    if (st) return st;
+    J.task_src = g.lo_src;
+    J.task_dst = g.lo_dst;
+    J.n_tasks = g.n_lo;
+  } else {
+    if (!g.sym.src) {
+      std::vector<int32_t> src(g.host.col.size());
+      for (int64_t u = 0; u < n; ++u)
+        for (int64_t q = g.host.rp[u]; q < g.host.rp[u + 1]; ++q) src[q] = (int32_t)u;
+      st = dev_upload(c, &g.sym.src, src.data(), src.size());
+      if (st) return st;
+      g.bytes += src.size() * 4;
+    }
+    J.task_src = g.sym.src;
+    J.task_dst = g.sym.col;
+    J.n_tasks = g.sym.nnz;
+  }
+  js.plans.push_back(hp.plan);
+  js.jobs.push_back(J);
+  js.need_words.push_back((int64_t)hp.n_buffers * cap);
+  qw.n_jobs += 1;
+  return GPM_OK;
+}
+
+static void named(const char* name, gpm_pattern* p);
+
+// k-motif counting (Sec. 2.1): fused triangle-rooted edge job, degree job,
+// 4-clique on the DAG and the 4-cycle plan (kernel fission, Sec. 5.3).
+static gpm_status add_motif_jobs(gpm_ctx* c, Graph& g, int k, JobPlanSet& js, QueryWork& qw) {
+  if (k != 3 && k != 4) return fail(c, GPM_E_INVAL, "motif size must be 3 or 4");
+  if (g.dag_only) return fail(c, GPM_E_UNSUPPORTED, "motifs need the symmetric graph");
+  qw.kind = GPM_QUERY_MOTIFS;
+  qw.k = k;
+  if (g.m == 0) { qw.has_constant = true; qw.constant = 0; return GPM_OK; }
+  gpm_status st = ensure_lower(c, g);
+  if (st) return st;
+  // slot order: [degree terms] [edge terms] [clique] [cycle4]
+  {
+    Job J{};
+    J.kind = kJobVertexDeg;
+    J.rp = g.sym.rp;
+    J.col = g.sym.col;
+    J.vertex_tasks = 1;
+    J.n_tasks = g.host.n;
+    J.chunk = default_chunk(c, kJobVertexDeg);
+    js.jobs.push_back(J);
+    js.need_words.push_back(0);
+  }
+  {
+    Job J{};
+    J.kind = kJobEdgeTri;
+    J.rp = g.sym.rp;
+    J.col = g.sym.col;
+    J.task_src = g.lo_src;
+    J.task_dst = g.lo_dst;
+    J.n_tasks = g.n_lo;
+    J.chunk = default_chunk(c, kJobEdgeTri);
+    js.jobs.push_back(J);
+    js.need_words.push_back(0);
+  }
+  qw.n_jobs += 2;
+  if (k == 4) {
+    gpm_pattern p;
+    QueryWork tmp;
+    gpm_pattern_clique(4, &p);
+    st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
+    if (st) return st;
+    if (tmp.has_constant) {  // no job was added: add an empty placeholder
+      Job J{};
+      J.kind = kJobVertexDeg;
+      J.rp = g.sym.rp;
+      J.col = g.sym.col;
+      J.vertex_tasks = 1;
+      J.n_tasks = 0;
+      J.chunk = 1;
+      js.jobs.push_back(J);
+      js.need_words.push_back(0);
+    }
+    named("cycle4", &p);
+    tmp = QueryWork{};
+    st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
+    if (st) return st;
+    if (tmp.has_constant) {
+      Job J{};
+      J.kind = kJobVertexDeg;
+      J.rp = g.sym.rp;
+      J.col = g.sym.col;
+      J.vertex_tasks = 1;
+      J.n_tasks = 0;
+      J.chunk = 1;
+      js.jobs.push_back(J);
+      js.need_words.push_back(0);
+    }
+    qw.n_jobs += 2;
+  }
+  return GPM_OK;
+}
+
+// Combine a query's job slots into its results.
+static void finish_query(const QueryWork& qw, const unsigned long long* res, uint64_t out[6]) {
+  for (int i = 0; i < 6; ++i) out[i] = 0;
+  if (qw.has_constant) {
+    if (qw.kind == GPM_QUERY_COUNT) out[0] = qw.constant;
+    return;
+  }
+  auto slot = [&](int j, int f) { return (uint64_t)res[(size_t)(qw.first_job + j) * kResultFields + f]; };
+  if (qw.kind == GPM_QUERY_COUNT) {
+    out[0] = slot(0, 0);
+    return;
+  }
+  const uint64_t sum_c2 = slot(0, 0), n_s3 = slot(0, 1);
+  const uint64_t three_t = slot(1, 0), n_d = slot(1, 1), two_tt = slot(1, 2), pmid = slot(1, 3);
+  const uint64_t T = three_t / 3;
+  if (qw.k == 3) {
+    out[0] = sum_c2 - 3 * T;  // induced wedges
+    out[1] = T;
+    return;
+  }
+  // non-induced 4-vertex counts -> induced (unitriangular inclusion relation)
+  const uint64_t n_k4 = slot(2, 0), n_c4 = slot(3, 0);
+  const uint64_t n_tt = two_tt / 2, n_p4 = pmid - 3 * T;
+  const uint64_t i_k4 = n_k4;
+  const uint64_t i_d = n_d - 6 * i_k4;
+  const uint64_t i_c4 = n_c4 - i_d - 3 * i_k4;
+  const uint64_t i_tt = n_tt - 4 * i_d - 12 * i_k4;
+  const uint64_t i_s3 = n_s3 - i_tt - 2 * i_d - 4 * i_k4;
+  const uint64_t i_p4 = n_p4 - 4 * i_c4 - 2 * i_tt - 6 * i_d - 12 * i_k4;
+  out[0] = i_p4; out[1] = i_s3; out[2] = i_c4; out[3] = i_tt; out[4] = i_d; out[5] = i_k4;
+}
+
+// ---------------------------------------------------------------------------
+// launching
+// ---------------------------------------------------------------------------
+
+static gpm_status slot_init(gpm_ctx* c, Slot& s, hipStream_t user) {
+  if (s.ev0) return GPM_OK;
+  if (user || &s == &c->slots[0]) {
+    s.stream = user;
+    s.own_stream = false;
+  } else {
+    HIP_TRY(c, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+    s.own_stream = true;
+  }
+  HIP_TRY(c, hipEventCreate(&s.ev0));
+  HIP_TRY(c, hipEventCreate(&s.ev1));
+  return GPM_OK;
+}
+
+static void slot_free(Slot& s) {
+  if (s.stream && s.own_stream) (void)hipStreamSynchronize(s.stream);
+  dev_free(s.d_meta);
+  dev_free(s.d_res);
+  dev_free(s.d_fbuf);
+  if (s.h_stage) (void)hipHostFree(s.h_stage);
+  if (s.h_res) (void)hipHostFree(s.h_res);
+  if (s.ev0) (void)hipEventDestroy(s.ev0);
+  if (s.ev1) (void)hipEventDestroy(s.ev1);
+  if (s.stream && s.own_stream) (void)hipStreamDestroy(s.stream);
+  s = Slot{};
+}
+
+static gpm_status grow_dev(gpm_ctx* c, void** p, size_t* have, size_t need) {
+  if (*have >= need) return GPM_OK;
+  dev_free(*p);
+  *p = nullptr;
+  *have = 0;
+  size_t n = std::max(need, (size_t)4096);
+  HIP_TRY(c, hipMalloc(p, n));
+  *have = n;
+  return GPM_OK;
+}
+
+static gpm_status grow_host(gpm_ctx* c, void** p, size_t* have, size_t need) {
+  if (*have >= need) return GPM_OK;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  *have = 0;
+  size_t n = std::max(need, (size_t)4096);
+  HIP_TRY(c, hipHostMalloc(p, n, hipHostMallocDefault));
+  *have = n;
+  return GPM_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct LaunchPlan {
+  uint32_t kinds = 0;
+  int first = 0, count = 0;   // jobs [first, first+count)
+  int64_t chunks = 0;
+  int blocks = 0;
+  std::vector<int64_t> jbeg;  // count + 1
+  int64_t qbeg[kQueues + 1];
+};
+
+// Split the jobs of js into launches: one launch per job kind (kernel
+// fission) when `fission`, else one launch for everything.  Jobs are
+// reordered so that every launch's jobs are contiguous.
+static std::vector<LaunchPlan> plan_launches(JobPlanSet& js, std::vector<int>& perm,
+                                             bool fission) {
+  const int nj = (int)js.jobs.size();
+  perm.resize(nj);
+  for (int i = 0; i < nj; ++i) perm[i] = i;
+  if (fission) std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+    return js.jobs[a].kind < js.jobs[b].kind;
+  });
+  std::vector<LaunchPlan> out;
+  for (int i = 0; i < nj; ++i) {
+    const Job& J = js.jobs[perm[i]];
+    uint32_t kb = 1u << J.kind;
+    if (out.empty() || (fission && out.back().kinds != kb)) {
+      LaunchPlan L;
+      L.first = i;
+      L.kinds = kb;
+      out.push_back(L);
+    }
+    LaunchPlan& L = out.back();
+    L.kinds |= kb;
+    L.count++;
+  }
+  return out;
+}
+
+// Size, stage and enqueue the launches of one group on slot s.  Results land
+// in s.h_res (pinned) when s.ev1 completes.
+static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission,
+                               size_t frontier_budget, size_t* frontier_used) {
+  gpm_status st = slot_init(c, s, s.stream);
+  if (st) return st;
+  std::vector<int> perm;
+  std::vector<LaunchPlan> launches = plan_launches(js, perm, fission);
+  const int nj = (int)js.jobs.size();
+  std::vector<Job> jobs(nj);
+  std::vector<int64_t> need(nj);
+  for (int i = 0; i < nj; ++i) {
+    jobs[i] = js.jobs[perm[i]];
+    need[i] = js.need_words[perm[i]];
+    jobs[i].slot = perm[i];  // result slot = the job's original index
+  }
+
+  // LDS tile of the clique kernel: U | F_2 .. F_{k-2} | P per wave
+  bool any_clique = false;
+  int kmax = 3;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].kind == kJobClique) {
+      any_clique = true;
+      kmax = std::max(kmax, (int)jobs[i].k);
+    }
+  int32_t lcap = 0, lds_words = 0;
+  if (any_clique) {
+    auto words = [&](int32_t cap) {
+      return (int32_t)align_up((size_t)cap * (1 + std::max(kmax - 3, 0)) + cap + 1, 4);
+    };
+    lcap = lds_tile(c);
+    lds_words = words(lcap);
+    while ((size_t)lds_words * 4 * kWavesPerBlock > 60 * 1024 && lcap > 32) {
+      lcap /= 2;
+      lds_words = words(lcap);
+    }
+    // tasks whose N+(u) exceeds the tile keep their sets in HBM
+    for (int i = 0; i < nj; ++i)
+      if (jobs[i].kind == kJobClique && jobs[i].cap > lcap)
+        need[i] = (int64_t)(std::max((int)jobs[i].k - 3, 0) + 1) * jobs[i].cap + 1;
+  }
+
+  // frontier sizing (adaptive buffering): one region of `stride` words per wave
+  int64_t stride = 0;
+  for (int i = 0; i < nj; ++i) stride = std::max(stride, need[i]);
+  stride = (int64_t)align_up((size_t)stride, 64);
+  const int64_t wpc = c->opt_waves_per_cu > 0 ? c->opt_waves_per_cu : 16;
+  int64_t max_resident = (int64_t)c->cus * wpc;
+  int64_t waves = max_resident;
+  if (stride > 0) {
+    gpm_status s2 = gpm_frontier_waves((int64_t)frontier_budget, 1, stride, max_resident,
+                                       max_resident, &waves);
+    if (s2) return fail(c, GPM_E_NOMEM, "frontier buffers do not fit the memory budget");
+  }
+  waves = std::max<int64_t>(kWavesPerBlock, waves / kWavesPerBlock * kWavesPerBlock);
+  const int blocks = (int)(waves / kWavesPerBlock);
+  const size_t fbytes = (size_t)waves * (size_t)stride * 4;
+  if (fbytes) {
+    st = grow_dev(c, (void**)&s.d_fbuf, &s.d_fbuf_bytes, fbytes);
+    if (st) return st;
+  }
+  *frontier_used = fbytes;
+
+  const size_t lds_bytes = (size_t)lds_words * 4 * kWavesPerBlock;
+
+  // chunk ranges and queues
+  for (auto& L : launches) {
+    L.jbeg.assign(L.count + 1, 0);
+    for (int i = 0; i < L.count; ++i) {
+      const Job& J = jobs[L.first + i];
+      int64_t ch = J.n_tasks > 0 ? (J.n_tasks + J.chunk - 1) / J.chunk : 0;
+      L.jbeg[i + 1] = L.jbeg[i] + ch;
+    }
+    L.chunks = L.jbeg[L.count];
+    for (int q = 0; q <= kQueues; ++q) L.qbeg[q] = L.chunks * q / kQueues;
+    L.blocks = blocks;
+  }
+
+  // staging: jobs | plans | per launch (jbeg, qbeg)
+  size_t off_jobs = 0;
+  size_t off_plans = align_up(off_jobs + sizeof(Job) * nj, 256);
+  size_t off_l = align_up(off_plans + sizeof(Plan) * std::max<size_t>(js.plans.size(), 1), 256);
+  std::vector<size_t> off_jbeg(launches.size()), off_qbeg(launches.size());
+  size_t cur = off_l;
+  for (size_t i = 0; i < launches.size(); ++i) {
+    off_jbeg[i] = cur;
+    cur = align_up(cur + 8 * launches[i].jbeg.size(), 64);
+    off_qbeg[i] = cur;
+    cur = align_up(cur + 8 * (kQueues + 1), 64);
+  }
+  const size_t meta_bytes = cur;
+  st = grow_host(c, &s.h_stage, &s.h_stage_bytes, meta_bytes);
+  if (st) return st;
+  st = grow_dev(c, &s.d_meta, &s.d_meta_bytes, meta_bytes);
+  if (st) return st;
+  char* h = (char*)s.h_stage;
+  std::memcpy(h + off_jobs, jobs.data(), sizeof(Job) * nj);
+  if (!js.plans.empty()) std::memcpy(h + off_plans, js.plans.data(), sizeof(Plan) * js.plans.size());
+  for (size_t i = 0; i < launches.size(); ++i) {
+    std::memcpy(h + off_jbeg[i], launches[i].jbeg.data(), 8 * launches[i].jbeg.size());
+    std::memcpy(h + off_qbeg[i], launches[i].qbeg, 8 * (kQueues + 1));
+  }
+  // device result words: results [nj * 8] | queues [launches * 8 * 16] | counters [4]
+  const size_t res_words = (size_t)nj * kResultFields;
+  const size_t q_words = launches.size() * kQueues * kQueueStride;
+  const size_t all_words = res_words + q_words + 4;
+  {
+    size_t have = s.d_res_words * 8;
+    st = grow_dev(c, (void**)&s.d_res, &have, all_words * 8);
+    if (st) return st;
+    s.d_res_words = have / 8;
+    size_t hh = s.h_res_words * 8;
+    st = grow_host(c, (void**)&s.h_res, &hh, all_words * 8);
+    if (st) return st;
+    s.h_res_words = hh / 8;
+  }
+  char* dm = (char*)s.d_meta;
+  HIP_TRY(c, hipMemcpyAsync(dm, h, meta_bytes, hipMemcpyHostToDevice, s.stream));
+  if (launch_fill_u64(s.d_res, (int64_t)all_words, 0ull, s.stream))
+    return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+  HIP_TRY(c, hipEventRecord(s.ev0, s.stream));
+  int n_launch = 0;
+  for (size_t i = 0; i < launches.size(); ++i) {
+    const LaunchPlan& L = launches[i];
+    if (L.chunks == 0) continue;
+    KernelArgs a{};
+    a.jobs = (const Job*)(dm + off_jobs) + L.first;
+    a.job_chunk_begin = (const int64_t*)(dm + off_jbeg[i]);
+    a.n_jobs = L.count;
+    a.lds_cap = lcap;
+    a.plans = (const Plan*)(dm + off_plans);
+    a.queue_begin = (const int64_t*)(dm + off_qbeg[i]);
+    a.queue_cnt = s.d_res + res_words + i * kQueues * kQueueStride;
+    a.results = s.d_res;
+    a.counters = s.d_res + res_words + q_words;
+    a.fbuf = fbytes ? s.d_fbuf : nullptr;
+    a.wave_stride = stride;
+    a.lds_words = (L.kinds & kKindClique) ? lds_words : 0;
+    size_t lb = (L.kinds & kKindClique) ? lds_bytes : 0;
+    int e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
+    if (e) return fail(c, GPM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
+    ++n_launch;
+  }
+  HIP_TRY(c, hipEventRecord(s.ev1, s.stream));
+  HIP_TRY(c, hipMemcpyAsync(s.h_res, s.d_res, all_words * 8, hipMemcpyDeviceToHost, s.stream));
+  s.n_jobs = nj;
+  s.n_launch = n_launch;
+  s.counters_off = res_words + q_words;
+  c->stats.waves = waves;
+  c->stats.frontier_bytes = (int64_t)fbytes;
+  c->stats.launches = n_launch;
+  int64_t tasks = 0;
+  for (auto& J : jobs) tasks += J.n_tasks;
+  c->stats.tasks = tasks;
+  c->stats.chunk = nj ? jobs[0].chunk : 0;
+  return GPM_OK;
+}
+
+static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
+  HIP_TRY(c, hipStreamSynchronize(s.stream));
+  float ms = 0.f;
+  if (s.n_launch > 0) HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
+  c->stats.kernel_ms = ms;
+  if (c->opt_count_elements) {
+    c->stats.elements = (int64_t)s.h_res[s.counters_off];
+    c->stats.list_fetches = (int64_t)s.h_res[s.counters_off + 1];
+  }
+  return GPM_OK;
+}
+
+// Run a synchronous group of queries on slot 0 (the user's stream).
+static gpm_status run_sync(gpm_ctx* c, JobPlanSet& js, std::vector<QueryWork>& qs,
+                           bool fission, uint64_t* outs) {
+  auto t0 = std::chrono::steady_clock::now();
+  Slot& s = c->slots[0];
+  s.stream = c->user_stream;
+  c->stats = gpm_stats{};
+  c->stats.elements = -1;
+  c->stats.list_fetches = -1;
+  if (js.jobs.empty()) {
+    for (size_t i = 0; i < qs.size(); ++i) finish_query(qs[i], nullptr, outs + 6 * i);
+    c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return GPM_OK;
+  }
+  size_t used = 0;
+  size_t budget = c->budget > c->serve_frontier_in_use ? c->budget - c->serve_frontier_in_use : 0;
+  gpm_status st = launch_group(c, s, js, fission, budget, &used);
+  if (st) return st;
+  st = finish_sync(c, s);
+  if (st) return st;
+  for (size_t i = 0; i < qs.size(); ++i) finish_query(qs[i], s.h_res, outs + 6 * i);
+  c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return GPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// built-in patterns
+// ---------------------------------------------------------------------------
+
+static void set_edges(gpm_pattern* p, int k, std::initializer_list<std::pair<int, int>> e) {
+  std::memset(p, 0, sizeof(*p));
+  p->k = k;
+  for (auto& x : e) {
+    p->edges[2 * p->n_edges] = x.first;
+    p->edges[2 * p->n_edges + 1] = x.second;
+    p->n_edges++;
+  }
+}
+
+static void named(const char* name, gpm_pattern* p) {
+  std::string s(name);
+  if (s == "edge") set_edges(p, 2, {{0, 1}});
+  else if (s == "wedge") set_edges(p, 3, {{0, 1}, {0, 2}});
+  else if (s == "triangle") gpm_pattern_clique(3, p);
+  else if (s == "path4") set_edges(p, 4, {{0, 1}, {1, 2}, {2, 3}});
+  else if (s == "star3") set_edges(p, 4, {{0, 1}, {0, 2}, {0, 3}});
+  else if (s == "cycle4") set_edges(p, 4, {{0, 1}, {1, 2}, {2, 3}, {3, 0}});
+  else if (s == "tailed_triangle") set_edges(p, 4, {{0, 1}, {1, 2}, {0, 2}, {2, 3}});
+  else if (s == "diamond") set_edges(p, 4, {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}});
+  else if (s == "clique4") gpm_pattern_clique(4, p);
+  else if (s == "clique5") gpm_pattern_clique(5, p);
+  else p->k = 0;
+}
+
+// ---------------------------------------------------------------------------
+// serving
+// ---------------------------------------------------------------------------
+
+static gpm_status build_query(gpm_ctx* c, const gpm_query& q, JobPlanSet& js, QueryWork& qw) {
+  Graph* g = find_graph(c, q.graph_id);
+  if (!g) return fail(c, GPM_E_INVAL, "unknown graph id");
+  qw = QueryWork{};
+  qw.kind = q.kind;
+  qw.first_job = (int)js.jobs.size();
+  if (q.kind == GPM_QUERY_COUNT) {
+    if (q.mode_or_k != GPM_VERTEX_INDUCED && q.mode_or_k != GPM_EDGE_INDUCED)
+      return fail(c, GPM_E_INVAL, "bad induced mode");
+    return add_count_jobs(c, *g, q.pattern, q.mode_or_k, js, qw);
+  }
+  if (q.kind == GPM_QUERY_MOTIFS) return add_motif_jobs(c, *g, q.mode_or_k, js, qw);
+  return fail(c, GPM_E_INVAL, "bad query kind");
+}
+
+static int n_serve_slots(const gpm_ctx* c) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSlots, c->opt_serve_slots));
+}
+
+// Collect finished launches, then admit pending queries into free slots.
+static gpm_status progress(gpm_ctx* c) {
+  const int ns = n_serve_slots(c);
+  for (int i = 1; i <= ns; ++i) {
+    Slot& s = c->slots[i];
+    if (!s.busy) continue;
+    hipError_t e = hipEventQuery(s.ev1);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) return fail(c, GPM_E_DEVICE, std::string("serving launch: ") + hipGetErrorString(e));
+    HIP_TRY(c, hipStreamSynchronize(s.stream));  // result copy queued after ev1
+    for (auto& qw : s.queries) {
+      std::array<uint64_t, 6> r{};
+      finish_query(qw, s.h_res, r.data());
+      c->done[qw.ticket] = r;
+    }
+    s.queries.clear();
+    s.busy = false;
+    c->serve_frontier_in_use -= s.frontier_bytes_in_use;
+    s.frontier_bytes_in_use = 0;
+  }
+  for (int i = 1; i <= ns && !c->pending.empty(); ++i) {
+    Slot& s = c->slots[i];
+    if (s.busy) continue;
+    gpm_status st = slot_init(c, s, nullptr);
+    if (st) return st;
+    size_t avail = c->budget > c->serve_frontier_in_use ? c->budget - c->serve_frontier_in_use : 0;
+    // continuous batching: every pending query (up to max_batch) joins this launch
+    JobPlanSet js;
+    std::vector<QueryWork> qs;
+    int taken = 0;
+    while (!c->pending.empty() && taken < c->opt_max_batch) {
+      Pending pq = c->pending.front();
+      QueryWork qw;
+      size_t before = js.jobs.size();
+      size_t pbefore = js.plans.size();
+      st = build_query(c, pq.q, js, qw);
+      if (st) {
+        // a query that cannot run completes with an error marker (all ones)
+        js.jobs.resize(before);
+        js.need_words.resize(before);
+        js.plans.resize(pbefore);
+        std::array<uint64_t, 6> r;
+        r.fill(~0ull);
+        c->done[pq.ticket] = r;
+        c->pending.pop_front();
+        continue;
+      }
+      // admission by frontier memory: the group's per-wave region must leave
+      // room for a useful number of waves
+      int64_t stride = 0;
+      for (auto w : js.need_words) stride = std::max(stride, w);
+      size_t min_bytes = (size_t)align_up((size_t)stride, 64) * 4 * (size_t)(c->cus);
+      if (taken > 0 && min_bytes > avail) {
+        js.jobs.resize(before);
+        js.need_words.resize(before);
+        js.plans.resize(pbefore);
+        break;
+      }
+      qw.ticket = pq.ticket;
+      qs.push_back(qw);
+      c->pending.pop_front();
+      ++taken;
+    }
+    if (qs.empty()) continue;
+    bool any_jobs = !js.jobs.empty();
+    if (!any_jobs) {
+      for (auto& qw : qs) {
+        std::array<uint64_t, 6> r{};
+        finish_query(qw, nullptr, r.data());
+        c->done[qw.ticket] = r;
+      }
+      continue;
+    }
+    size_t used = 0;
+    st = launch_group(c, s, js, false, avail, &used);
+    if (st) return st;
+    s.queries = qs;
+    s.busy = true;
+    s.frontier_bytes_in_use = used;
+    c->serve_frontier_in_use += used;
+  }
+  return GPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+gpm_status gpm_create(gpm_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes) {
+  if (!out) return GPM_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GPM_E_DEVICE;
+  if (device < 0 || device >= ndev) return GPM_E_INVAL;
+  if (hipSetDevice(device) != hipSuccess) return GPM_E_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return GPM_E_DEVICE;
+  auto* c = new (std::nothrow) gpm_ctx();
+  if (!c) return GPM_E_NOMEM;
+  c->device = device;
+  c->user_stream = (hipStream_t)hip_stream;
+  c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  size_t freeb = 0, total = 0;
+  if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
+    delete c;
+    return GPM_E_DEVICE;
+  }
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : freeb / 10 * 9;
+  c->slots[0].stream = c->user_stream;
+  *out = c;
+  return GPM_OK;
+}
+
+gpm_status gpm_destroy(gpm_ctx* c) {
+  if (!c) return GPM_OK;
+  (void)hipSetDevice(c->device);
+  for (auto& s : c->slots) slot_free(s);
+  for (auto& kv : c->graphs) free_graph(*kv.second);
+  delete c;
+  return GPM_OK;
+}
+
+const char* gpm_last_error(const gpm_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
+  if (!c || !key) return GPM_E_INVAL;
+  std::string k(key);
+  if (k == "granularity") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "granularity 0..2"); c->opt_granularity = v; }
+  else if (k == "chunk") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "chunk"); c->opt_chunk = v; }
+  else if (k == "waves_per_cu") { if (v < 0 || v > 32) return fail(c, GPM_E_INVAL, "waves_per_cu 0..32"); c->opt_waves_per_cu = v; }
+  else if (k == "setop") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "setop 0..2"); c->opt_setop = v; }
+  else if (k == "clique_lds") c->opt_clique_lds = v != 0;
+  else if (k == "lds_tile") { if (v < 0 || v > 4096) return fail(c, GPM_E_INVAL, "lds_tile 0..4096"); c->opt_lds_tile = v; }
+  else if (k == "rename") { if (v < -1 || v > 2) return fail(c, GPM_E_INVAL, "rename -1..2"); c->opt_rename = v; }
+  else if (k == "count_elements") c->opt_count_elements = v != 0;
+  else if (k == "autotune") c->opt_autotune = v != 0;
+  else if (k == "max_batch") { if (v < 1) return fail(c, GPM_E_INVAL, "max_batch >= 1"); c->opt_max_batch = v; }
+  else if (k == "serve_slots") { if (v < 1 || v > kMaxSlots) return fail(c, GPM_E_INVAL, "serve_slots 1..4"); c->opt_serve_slots = v; }
+  else if (k == "max_pending") { if (v < 1) return fail(c, GPM_E_INVAL, "max_pending >= 1"); c->opt_max_pending = v; }
+  else if (k == "budget") { if (v < 0) return fail(c, GPM_E_INVAL, "budget >= 0"); c->budget = (size_t)v; }
+  else return fail(c, GPM_E_INVAL, "unknown option " + k);
+  return GPM_OK;
+}
+
+gpm_status gpm_get_stats(const gpm_ctx* c, gpm_stats* out) {
+  if (!c || !out) return GPM_E_INVAL;
+  *out = c->stats;
+  return GPM_OK;
+}
+
+gpm_status gpm_load_csr(gpm_ctx* c, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                        const int32_t* col, uint32_t flags, int32_t* graph_id_out) {
+  if (!c || !graph_id_out) return GPM_E_INVAL;
+  if (n < 0 || nnz < 0 || n >= (int64_t)INT32_MAX) return fail(c, GPM_E_INVAL, "bad n or nnz");
+  if (!row_ptr || (nnz > 0 && !col)) return fail(c, GPM_E_INVAL, "null CSR array");
+  const bool dag = (flags & GPM_CSR_DAG) != 0;
+  const bool sym = (flags & GPM_CSR_SYMMETRIC) != 0 || !dag;
+  if (dag && (flags & GPM_CSR_SYMMETRIC)) return fail(c, GPM_E_INVAL, "SYMMETRIC and DAG both set");
+  HIP_TRY(c, hipSetDevice(c->device));
+  auto g = std::make_unique<Graph>();
+  g->dag_only = dag;
+  HostCSR& h = g->host;
+  h.n = n;
+  h.rp.resize(n + 1);
+  h.col.resize(nnz);
+  if (flags & GPM_PTRS_DEVICE) {
+    HIP_TRY(c, hipMemcpy(h.rp.data(), row_ptr, (n + 1) * 8, hipMemcpyDeviceToHost));
+    if (nnz) HIP_TRY(c, hipMemcpy(h.col.data(), col, nnz * 4, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(h.rp.data(), row_ptr, (n + 1) * 8);
+    if (nnz) std::memcpy(h.col.data(), col, nnz * 4);
+  }
+  // canonical form (Table 3's note: no loops, no duplicates; sorted lists, Sec. 3)
+  if (h.rp[0] != 0 || h.rp[n] != nnz) return fail(c, GPM_E_CSR, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  for (int64_t u = 0; u < n; ++u) {
+    if (h.rp[u + 1] < h.rp[u]) return fail(c, GPM_E_CSR, "row_ptr not monotone");
+    for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) {
+      int32_t v = h.col[p];
+      if (v < 0 || v >= n) return fail(c, GPM_E_CSR, "neighbour id out of range");
+      if (v == u) return fail(c, GPM_E_CSR, "self loop");
+      if (p > h.rp[u] && h.col[p - 1] >= v) return fail(c, GPM_E_CSR, "neighbour list unsorted or duplicated");
+    }
+  }
+  auto has = [&](int64_t u, int32_t v) {
+    return std::binary_search(h.col.begin() + h.rp[u], h.col.begin() + h.rp[u + 1], v);
+  };
+  if (flags & GPM_VALIDATE) {
+    for (int64_t u = 0; u < n; ++u)
+      for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) {
+        bool back = has(h.col[p], (int32_t)u);
+        if (sym && !back) return fail(c, GPM_E_CSR, "graph not symmetric");
+        if (dag && back) return fail(c, GPM_E_CSR, "DAG holds both directions of an edge");
+      }
+    if (dag) {  // acyclic (Kahn)
+      std::vector<int64_t> indeg(n, 0);
+      for (int64_t p = 0; p < nnz; ++p) indeg[h.col[p]]++;
+      std::vector<int64_t> q;
+      for (int64_t u = 0; u < n; ++u) if (!indeg[u]) q.push_back(u);
+      int64_t seen = 0;
+      while (!q.empty()) {
+        int64_t u = q.back();
+        q.pop_back();
+        ++seen;
+        for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p)
+          if (--indeg[h.col[p]] == 0) q.push_back(h.col[p]);
+      }
+      if (seen != n) return fail(c, GPM_E_CSR, "oriented graph has a cycle");
+    }
+  } else if (sym && (nnz & 1)) {
+    return fail(c, GPM_E_CSR, "symmetric graph with an odd number of entries");
+  }
+  g->m = dag ? nnz : nnz / 2;
+  if (!dag) {
+    gpm_status st = upload_view(c, h, false, &g->sym, &g->bytes);
+    if (st) { free_graph(*g); return st; }
+  }
+  int32_t id = c->next_graph++;
+  c->graphs[id] = std::move(g);
+  *graph_id_out = id;
+  return GPM_OK;
+}
+
+gpm_status gpm_unload(gpm_ctx* c, int32_t id) {
+  if (!c) return GPM_E_INVAL;
+  auto it = c->graphs.find(id);
+  if (it == c->graphs.end()) return fail(c, GPM_E_INVAL, "unknown graph id");
+  for (auto& s : c->slots)
+    if (s.busy) return fail(c, GPM_E_BUSY, "serving launches in flight");
+  (void)hipDeviceSynchronize();
+  free_graph(*it->second);
+  c->graphs.erase(it);
+  return GPM_OK;
+}
+
+gpm_status gpm_graph_info(gpm_ctx* c, int32_t id, gpm_graph_meta* out) {
+  if (!c || !out) return GPM_E_INVAL;
+  Graph* g = find_graph(c, id);
+  if (!g) return fail(c, GPM_E_INVAL, "unknown graph id");
+  gpm_status st = ensure_dag(c, *g);
+  if (st) return st;
+  out->n = g->host.n;
+  out->m = g->m;
+  out->max_degree = g->dag_only ? 0 : g->sym.max_deg;
+  out->max_out_degree = g->dag.max_deg;
+  out->device_bytes = (int64_t)g->bytes;
+  return GPM_OK;
+}
+
+gpm_status gpm_pattern_clique(int k, gpm_pattern* out) {
+  if (!out || k < 1 || k > GPM_MAX_K) return GPM_E_PATTERN;
+  std::memset(out, 0, sizeof(*out));
+  out->k = k;
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j) {
+      out->edges[2 * out->n_edges] = i;
+      out->edges[2 * out->n_edges + 1] = j;
+      out->n_edges++;
+    }
+  return GPM_OK;
+}
+
+gpm_status gpm_pattern_named(const char* name, gpm_pattern* out) {
+  if (!name || !out) return GPM_E_INVAL;
+  named(name, out);
+  return out->k ? GPM_OK : GPM_E_INVAL;
+}
+
+gpm_status gpm_pattern_from_edges(int k, int n_edges, const int32_t* edges, gpm_pattern* out) {
+  if (!out || (n_edges > 0 && !edges)) return GPM_E_INVAL;
+  if (n_edges < 0 || n_edges > GPM_MAX_PATTERN_EDGES) return GPM_E_PATTERN;
+  gpm_pattern p;
+  std::memset(&p, 0, sizeof(p));
+  p.k = k;
+  p.n_edges = n_edges;
+  for (int i = 0; i < 2 * n_edges; ++i) p.edges[i] = edges[i];
+  gpm_status st = validate_pattern(p, nullptr);
+  if (st) return st;
+  *out = p;
+  return GPM_OK;
+}
+
+gpm_status gpm_plan(const gpm_pattern* p, int mode, gpm_plan_info* out) {
+  if (!p || !out) return GPM_E_INVAL;
+  if (mode != GPM_VERTEX_INDUCED && mode != GPM_EDGE_INDUCED) return GPM_E_INVAL;
+  HostPlan hp;
+  gpm_status st = validate_pattern(*p, nullptr);
+  if (st) return st;
+  st = build_plan(*p, mode, is_clique(*p) && p->k >= 3, &hp, nullptr);
+  if (st) return st;
+  std::memset(out, 0, sizeof(*out));
+  out->k = hp.k;
+  out->clique = hp.clique;
+  out->aut = hp.aut;
+  out->root_bound = hp.plan.root_bound;
+  out->n_buffers = hp.n_buffers;
+  for (int d = 0; d < hp.k; ++d) out->order[d] = hp.order[d];
+  out->n_restrictions = (int)hp.restrictions.size();
+  for (size_t i = 0; i < hp.restrictions.size(); ++i) {
+    out->restrictions[2 * i] = hp.restrictions[i].first;
+    out->restrictions[2 * i + 1] = hp.restrictions[i].second;
+  }
+  return GPM_OK;
+}
+
+gpm_status gpm_frontier_waves(int64_t free_bytes, int32_t x_levels, int64_t cap_elems,
+                              int64_t n_tasks, int64_t max_resident, int64_t* waves_out) {
+  if (!waves_out || free_bytes < 0 || x_levels < 0 || cap_elems < 0 || n_tasks < 0 ||
+      max_resident < 1)
+    return GPM_E_INVAL;
+  const int64_t per = (int64_t)x_levels * cap_elems * 4;
+  int64_t w = per > 0 ? free_bytes / per : max_resident;
+  if (per > 0 && w < 1) return GPM_E_NOMEM;
+  w = std::min(w, std::max<int64_t>(n_tasks, 1));
+  w = std::min(w, max_resident);
+  *waves_out = w;
+  return GPM_OK;
+}
+
+gpm_status gpm_count(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, int mode,
+                     uint64_t* count_out) {
+  if (!c || !pattern || !count_out) return GPM_E_INVAL;
+  gpm_query q{};
+  q.graph_id = graph_id;
+  q.kind = GPM_QUERY_COUNT;
+  q.mode_or_k = mode;
+  q.pattern = *pattern;
+  HIP_TRY(c, hipSetDevice(c->device));
+  JobPlanSet js;
+  std::vector<QueryWork> qs(1);
+  gpm_status st = build_query(c, q, js, qs[0]);
+  if (st) return st;
+  uint64_t out[6];
+  st = run_sync(c, js, qs, true, out);
+  if (st) return st;
+  *count_out = out[0];
+  return GPM_OK;
+}
+
+gpm_status gpm_motifs(gpm_ctx* c, int32_t graph_id, int k, uint64_t* counts_out, size_t len) {
+  if (!c || !counts_out) return GPM_E_INVAL;
+  if ((k == 3 && len < 2) || (k == 4 && len < 6)) return fail(c, GPM_E_INVAL, "counts_out too short");
+  gpm_query q{};
+  q.graph_id = graph_id;
+  q.kind = GPM_QUERY_MOTIFS;
+  q.mode_or_k = k;
+  HIP_TRY(c, hipSetDevice(c->device));
+  JobPlanSet js;
+  std::vector<QueryWork> qs(1);
+  gpm_status st = build_query(c, q, js, qs[0]);
+  if (st) return st;
+  uint64_t out[6];
+  st = run_sync(c, js, qs, true, out);
+  if (st) return st;
+  for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts_out[i] = out[i];
+  return GPM_OK;
+}
+
+gpm_status gpm_count_batch(gpm_ctx* c, int32_t nq, const gpm_query* queries, uint64_t* outs) {
+  if (!c || nq < 0 || (nq > 0 && (!queries || !outs))) return GPM_E_INVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  JobPlanSet js;
+  std::vector<QueryWork> qs(nq);
+  for (int i = 0; i < nq; ++i) {
+    gpm_status st = build_query(c, queries[i], js, qs[i]);
+    if (st) return st;
+  }
+  return run_sync(c, js, qs, false, outs);
+}
+
+gpm_status gpm_submit(gpm_ctx* c, const gpm_query* q, int64_t* ticket_out) {
+  if (!c || !q || !ticket_out) return GPM_E_INVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if ((int64_t)c->pending.size() >= c->opt_max_pending) return fail(c, GPM_E_BUSY, "pending list full");
+  if (!find_graph(c, q->graph_id)) return fail(c, GPM_E_INVAL, "unknown graph id");
+  int64_t t = c->next_ticket++;
+  c->pending.push_back(Pending{*q, t});
+  *ticket_out = t;
+  return progress(c);
+}
+
+gpm_status gpm_poll(gpm_ctx* c, int64_t ticket, int* done_out, uint64_t* counts_out) {
+  if (!c || !done_out) return GPM_E_INVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  gpm_status st = progress(c);
+  if (st) return st;
+  auto it = c->done.find(ticket);
+  if (it == c->done.end()) {
+    *done_out = 0;
+    return GPM_OK;
+  }
+  if (counts_out)
+    for (int i = 0; i < 6; ++i) counts_out[i] = it->second[i];
+  c->done.erase(it);
+  *done_out = 1;
+  return GPM_OK;
+}
+
+gpm_status gpm_wait(gpm_ctx* c, int64_t ticket, int64_t timeout_ns, uint64_t* counts_out) {
+  if (!c) return GPM_E_INVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    int done = 0;
+    gpm_status st = gpm_poll(c, ticket, &done, counts_out);
+    if (st) return st;
+    if (done) return GPM_OK;
+    auto el = std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
+    if (timeout_ns >= 0 && el >= timeout_ns) return fail(c, GPM_E_TIMEOUT, "wait timed out");
+  }
+}
+
+gpm_status gpm_inflight(gpm_ctx* c, int64_t* count_out) {
+  if (!c || !count_out) return GPM_E_INVAL;
+  int64_t n = (int64_t)c->pending.size() + (int64_t)c->done.size();
+  for (auto& s : c->slots) n += (int64_t)s.queries.size();
+  *count_out = n;
+  return GPM_OK;
+}
+
+}  // extern "C"

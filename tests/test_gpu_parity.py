@@ -1,0 +1,234 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every count is an exact integer, so the bar is bit-exact equality.  Inputs
+are seeded synthetic graphs: structured families with closed forms, and
+random Erdos-Renyi / R-MAT / Chung-Lu graphs at sizes that span many chunks
+and ragged tails.
+"""
+import numpy as np
+import pytest
+
+from paper_2112_09761_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["triangle", "wedge", "path4", "star3", "cycle4", "tailed_triangle",
+         "diamond", "clique4", "clique5"]
+V, E = 0, 1
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2112_09761_amd import gpm
+    assert torch.cuda.is_available()
+    c = gpm.Context(0, torch.cuda.current_stream())
+    yield c
+    c.close()
+
+
+def graphs_small():
+    return [
+        synth.complete(9),
+        synth.complete_bipartite(5, 7),
+        synth.complete_multipartite([3, 4, 5, 2]),
+        synth.grid(6, 9),
+        synth.hypercube(5),
+        synth.star(40),
+        synth.path(30),
+        synth.cycle(17),
+        synth.erdos_renyi(60, 0.2, 101),
+        synth.rmat(8, 6, seed=102),
+        synth.chung_lu(500, 6.0, 2.1, 80.0, 1500, 103),
+        synth.disjoint_union(synth.complete(6), synth.empty(5), synth.cycle(4)),
+    ]
+
+
+@pytest.mark.parametrize("gi", range(12))
+def test_named_patterns_small(ctx, oracle, gi):
+    g = graphs_small()[gi]
+    gid = ctx.load(g)
+    try:
+        for name in NAMES:
+            for mode in (V, E):
+                got = ctx.count(gid, name, mode)
+                exp = oracle.count(g, name, mode == V)
+                assert got == exp, (g.name, name, mode, got, exp)
+    finally:
+        ctx.unload(gid)
+
+
+@pytest.mark.parametrize("gi", range(12))
+def test_motifs_small(ctx, oracle, gi):
+    g = graphs_small()[gi]
+    gid = ctx.load(g)
+    try:
+        assert ctx.motifs(gid, 3) == oracle.motifs3(g), g.name
+        assert ctx.motifs(gid, 4) == oracle.motifs4(g), g.name
+    finally:
+        ctx.unload(gid)
+
+
+@pytest.mark.parametrize("seed", range(1, 9))
+def test_er_triangle_workload(ctx, oracle, seed):
+    """Triangle counting on G(2000, 0.01), id-oriented oracle route."""
+    g = synth.workload_er_triangle(seed)
+    gid = ctx.load(g)
+    try:
+        assert ctx.count(gid, "triangle") == oracle.triangles(g, 0)
+    finally:
+        ctx.unload(gid)
+
+
+@pytest.mark.parametrize("mk", [
+    lambda: synth.rmat(12, 16, seed=201),
+    lambda: synth.erdos_renyi(3000, 0.01, 202),
+    lambda: synth.chung_lu(5000, 12.0, 2.1, 600.0, 30000, 203),
+])
+def test_medium_graphs_all_patterns(ctx, oracle, mk):
+    g = mk()
+    gid = ctx.load(g)
+    try:
+        for name in NAMES:
+            for mode in (V, E):
+                got = ctx.count(gid, name, mode)
+                exp = oracle.count(g, name, mode == V)
+                assert got == exp, (g.name, name, mode, got, exp)
+        assert ctx.motifs(gid, 4) == oracle.motifs4(g)
+    finally:
+        ctx.unload(gid)
+
+
+def random_pattern(rng, k):
+    while True:
+        edges = [(i, j) for i in range(k) for j in range(i + 1, k) if rng.random() < 0.5]
+        # connected?
+        adj = {i: set() for i in range(k)}
+        for a, b in edges:
+            adj[a].add(b)
+            adj[b].add(a)
+        seen, st = {0}, [0]
+        while st:
+            x = st.pop()
+            for y in adj[x]:
+                if y not in seen:
+                    seen.add(y)
+                    st.append(y)
+        if len(seen) == k:
+            return (k, edges)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_patterns(ctx, oracle, seed):
+    rng = np.random.default_rng(300 + seed)
+    g = synth.erdos_renyi(40, 0.3, 400 + seed)
+    gid = ctx.load(g)
+    try:
+        for k in (3, 4, 5, 6):
+            pat = random_pattern(rng, k)
+            for mode in (V, E):
+                got = ctx.count(gid, pat, mode)
+                exp = oracle.count_embed(g, pat, mode == V)
+                assert got == exp, (pat, mode, got, exp)
+    finally:
+        ctx.unload(gid)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6, 7, 8])
+def test_cliques_multipartite(ctx, k):
+    import itertools
+    import math
+    parts = [9, 7, 8, 6, 9, 5, 7, 8, 6]
+    g = synth.complete_multipartite(parts)
+    exp = sum(math.prod(c) for c in itertools.combinations(parts, k))
+    gid = ctx.load(g)
+    try:
+        assert ctx.count(gid, synth_clique(k)) == exp
+    finally:
+        ctx.unload(gid)
+
+
+def synth_clique(k):
+    return (k, [(i, j) for i in range(k) for j in range(i + 1, k)])
+
+
+def test_tuning_options_do_not_change_counts(ctx, oracle):
+    g = synth.rmat(11, 12, seed=501)
+    gid = ctx.load(g)
+    exp = {n: oracle.count(g, n, True) for n in ["clique4", "clique5", "cycle4", "diamond"]}
+    try:
+        for opt, vals in [("chunk", [1, 3, 64]), ("waves_per_cu", [1, 4, 32]),
+                          ("lds_tile", [32, 64, 4096]), ("clique_lds", [0]),
+                          ("granularity", [1])]:
+            for v in vals:
+                ctx.set_option(opt, v)
+                for n, e in exp.items():
+                    assert ctx.count(gid, n, V) == e, (opt, v, n)
+            ctx.set_option(opt, {"chunk": 0, "waves_per_cu": 0, "lds_tile": 0,
+                                 "clique_lds": 1, "granularity": 0}[opt])
+    finally:
+        ctx.unload(gid)
+
+
+def test_edge_cases(ctx):
+    from paper_2112_09761_amd import gpm
+    e = synth.empty(10)
+    gid = ctx.load(e)
+    assert ctx.count(gid, "triangle") == 0
+    assert ctx.count(gid, (1, [])) == 10
+    assert ctx.motifs(gid, 4) == [0] * 6
+    ctx.unload(gid)
+    k3 = synth.complete(3)
+    gid = ctx.load(k3)
+    assert ctx.count(gid, "clique4") == 0
+    assert ctx.count(gid, "edge") == 3
+    assert ctx.count(gid, "triangle") == 1
+    ctx.unload(gid)
+    z = synth.empty(0)
+    gid = ctx.load(z)
+    assert ctx.count(gid, "triangle") == 0
+    ctx.unload(gid)
+    with pytest.raises(gpm.GpmError):
+        ctx.count(12345, "triangle")
+
+
+def test_batch_equals_single(ctx, oracle):
+    from paper_2112_09761_amd import gpm
+    gs = [synth.rmat(9, 8, seed=600 + i) if i % 2 else synth.erdos_renyi(700, 0.02, 600 + i)
+          for i in range(10)]
+    ids = [ctx.load(g) for g in gs]
+    try:
+        qs = []
+        for gid in ids:
+            qs.append(gpm.motif_query(gid, 4))
+            qs.append(gpm.count_query(gid, "clique5", V))
+            qs.append(gpm.count_query(gid, "diamond", E))
+        res = ctx.count_batch(qs)
+        for i, g in enumerate(gs):
+            assert res[3 * i] == oracle.motifs4(g)
+            assert res[3 * i + 1] == oracle.cliques(g, 5)
+            assert res[3 * i + 2] == oracle.count(g, "diamond", False)
+    finally:
+        for gid in ids:
+            ctx.unload(gid)
+
+
+def test_serving_alone_vs_mix(ctx, oracle):
+    from paper_2112_09761_amd import gpm
+    gs = [synth.rmat(9 + i % 3, 8, seed=700 + i) for i in range(6)]
+    ids = [ctx.load(g) for g in gs]
+    pats = ["triangle", "clique4", "clique5", "cycle4", "diamond", "tailed_triangle"]
+    try:
+        rng = np.random.default_rng(7)
+        qs = [(int(rng.integers(0, len(ids))), pats[int(rng.integers(0, len(pats)))])
+              for _ in range(40)]
+        alone = [ctx.count(ids[a], p, E) for a, p in qs]
+        tickets = [ctx.submit(gpm.count_query(ids[a], p, E)) for a, p in qs]
+        mixed = [ctx.wait(t)[0] for t in tickets]
+        assert alone == mixed
+        for (a, p), x in zip(qs, alone):
+            assert x == oracle.count(gs[a], p, False)
+        assert ctx.inflight() == 0
+    finally:
+        for gid in ids:
+            ctx.unload(gid)

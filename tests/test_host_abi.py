@@ -1,0 +1,112 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, and its host-only logic (patterns, search plans, frontier sizing)
+behaves as the paper states.  No device call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2112_09761_amd import gpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "gpm.h")).read()
+    return sorted(set(re.findall(r"\b(gpm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gpm.lib()
+    names = declared_symbols()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(gpm.EXPORTS)
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(gpm.Pattern) == 4 * (2 + 56)
+    assert ctypes.sizeof(gpm.Query) == 16 + ctypes.sizeof(gpm.Pattern)
+
+
+def test_named_patterns():
+    for name, (k, ne) in {"edge": (2, 1), "wedge": (3, 2), "triangle": (3, 3),
+                          "path4": (4, 3), "star3": (4, 3), "cycle4": (4, 4),
+                          "tailed_triangle": (4, 4), "diamond": (4, 5),
+                          "clique4": (4, 6), "clique5": (5, 10)}.items():
+        p = gpm.pattern_named(name)
+        assert (p.k, p.n_edges) == (k, ne)
+    with pytest.raises(gpm.GpmError):
+        gpm.pattern_named("nonsense")
+
+
+def test_invalid_patterns_rejected():
+    for k, edges in [(4, [(0, 1), (2, 3)]), (3, [(0, 0)]), (3, [(0, 3)]),
+                     (9, [(i, i + 1) for i in range(8)]), (3, [(0, 1), (1, 0), (1, 2)])]:
+        with pytest.raises(gpm.GpmError) as e:
+            gpm.pattern_from_edges(k, edges)
+        assert e.value.status == -3
+
+
+def test_diamond_symmetry_order_worked_example():
+    """Sec. 2.2 / Fig. 4: the diamond's symmetry order is {v1 > v2, v3 > v4}
+    (1-based) under matching order u1, u2, u3, u4 (both degree-3 vertices
+    first)."""
+    import json
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "diamond_symmetry_order.json")))
+    p = gpm.pattern_from_edges(4, fx["pattern_edges"])
+    for mode in (0, 1):
+        pl = gpm.plan(p, mode)
+        assert pl["order"] == fx["matching_order"]
+        assert sorted(map(tuple, pl["restrictions"])) == sorted(map(tuple, fx["restrictions"]))
+        assert pl["root_bound"]  # v0 > v1 halves the root edge list (Sec. 7.2 (2))
+
+
+@pytest.mark.parametrize("name", ["wedge", "path4", "star3", "cycle4", "tailed_triangle",
+                                  "diamond", "clique4", "clique5"])
+def test_plan_properties(name, oracle):
+    """Buffers X <= k - 3; every restriction orders an earlier depth above a
+    later one; |Aut| matches the oracle's brute force."""
+    for mode in (0, 1):
+        pl = gpm.plan(name, mode)
+        k = pl["k"]
+        assert pl["n_buffers"] <= max(k - 3, 0)
+        depth = {v: d for d, v in enumerate(pl["order"])}
+        for a, b in pl["restrictions"]:
+            assert depth[a] < depth[b]
+        assert pl["aut"] == oracle.aut(name)
+        # matching order is connected
+        p = gpm.pattern_named(name)
+        adj = set(p.edge_list()) | {(b, a) for a, b in p.edge_list()}
+        for d in range(1, k):
+            assert any((pl["order"][d], pl["order"][e]) in adj for e in range(d))
+
+
+def test_stabiliser_chain_count_identity(oracle):
+    """The restrictions admit exactly one of the |Aut| automorphic images of
+    every embedding: counting the embeddings of P into P itself that satisfy
+    them gives 1 (T9-style check on the pattern as its own data graph)."""
+    import itertools
+    for name in ["wedge", "path4", "star3", "cycle4", "tailed_triangle", "diamond"]:
+        p = gpm.pattern_named(name)
+        pl = gpm.plan(p, 1)
+        k = p.k
+        E = set(p.edge_list()) | {(b, a) for a, b in p.edge_list()}
+        ok = 0
+        for perm in itertools.permutations(range(k)):
+            if all((perm[a], perm[b]) in E for a, b in p.edge_list()):
+                if all(perm[a] > perm[b] for a, b in pl["restrictions"]):
+                    ok += 1
+        assert ok == 1, name
+
+
+def test_frontier_sizing():
+    """Adaptive buffering, Sec. 7.2 (3): waves = min(Y / (X * Delta), |Omega|)."""
+    assert gpm.frontier_waves(10**9, 2, 1000, 10**9, 10**6) == 10**9 // (2 * 1000 * 4)
+    assert gpm.frontier_waves(10**9, 2, 1000, 50, 10**6) == 50
+    assert gpm.frontier_waves(10**9, 1, 10, 10**9, 4096) == 4096
+    assert gpm.frontier_waves(10**9, 0, 1000, 10**9, 4096) == 4096
+    with pytest.raises(gpm.GpmError):
+        gpm.frontier_waves(100, 1, 1000, 10, 10)
