@@ -1,0 +1,179 @@
+#!/usr/bin/env python
+"""Benchmark: exact 4-clique + 5-clique counting on the R-MAT scale-20 graph.
+
+One step = gpm_count(4-clique) + gpm_count(5-clique) on the resident,
+prepared graph (2^20 vertices, edge factor 16, (a,b,c) = (0.57, 0.19, 0.19),
+degree-oriented).  Preparation (generation, upload, orientation) happens
+before the timed region, as in the paper's evaluation.
+
+Prints ONE JSON line: intersected elements/s over the timed steps, the
+roofline of the dominant kernel (the 5-clique launch) and the CPU oracle's
+rate on a bounded sample.  Other workloads (--workload batch | serve |
+triangle) print their own line.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="clique",
+                    choices=["clique", "triangle", "batch", "serve"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--option", action="append", default=[],
+                    help="library option key=value (tuning sweeps)")
+    return ap.parse_args()
+
+
+def golden(name):
+    p = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+    if os.path.exists(p):
+        with open(p) as f:
+            return json.load(f)
+    return None
+
+
+def algorithmic_bytes(st):
+    # 4 B per intersected element, 16 B per neighbour-list fetch (row offsets),
+    # 4 B per frontier element written
+    return 4 * st["elements"] + 16 * st["list_fetches"] + 4 * st["frontier_written"]
+
+
+def cpu_baseline_clique4(g, elements4):
+    from oracle import pyoracle
+    t = time.perf_counter()
+    c = pyoracle.cliques(g, 4, 1)
+    dt = time.perf_counter() - t
+    return {"value": elements4 / dt, "unit": "elem/s", "cores": pyoracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"4-clique count of the full graph (one of the step's two counts): "
+                      f"{dt:.1f} s, count {c}; elements = the method's intersected "
+                      f"elements for that count"}, c
+
+
+def run_clique(args, ctx, torch):
+    from paper_2112_09761_amd import synth
+    g = synth.workload_rmat_s20()
+    gid = ctx.load(g)
+    info = ctx.graph_info(gid)  # forces the degree orientation (untimed)
+    # instrumented pass (never timed): the method's work per count
+    ctx.set_option("count_elements", 1)
+    inst = {}
+    for k in (4, 5):
+        ctx.count(gid, (k, [(i, j) for i in range(k) for j in range(i + 1, k)]))
+        inst[k] = ctx.stats()
+    ctx.set_option("count_elements", 0)
+    pats = {k: (k, [(i, j) for i in range(k) for j in range(i + 1, k)]) for k in (4, 5)}
+    for _ in range(args.warmup):
+        for k in (4, 5):
+            ctx.count(gid, pats[k])
+    torch.cuda.synchronize()
+    kms = {4: [], 5: []}
+    counts = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for k in (4, 5):
+            counts[k] = ctx.count(gid, pats[k])
+            kms[k].append(ctx.stats()["kernel_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    E = inst[4]["elements"] + inst[5]["elements"]
+    value = E * args.steps / dt
+    gold = golden("rmat_s20")
+    parity = None
+    if gold and gold["sha256"] == g.sha256():
+        parity = (counts[4] == gold["counts"]["clique4"] and counts[5] == gold["counts"]["clique5"])
+    k5 = statistics.mean(kms[5])
+    b5 = algorithmic_bytes(inst[5])
+    achieved = b5 / (k5 * 1e-3) / 1e9
+    out = {
+        "metric": "intersected elements/s, exact 4-clique + 5-clique counts",
+        "value": value, "unit": "elem/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "rmat_s20_ef16_clique4_clique5", "n": g.n, "m": g.m,
+                   "max_degree": info["max_degree"],
+                   "max_out_degree": info["max_out_degree"],
+                   "orientation": "degree", "counts_per_step": 2},
+        "counts": {"clique4": counts[4], "clique5": counts[5]},
+        "parity_vs_stored_oracle": parity,
+        "ms_per_count": {"clique4": statistics.mean(kms[4]), "clique5": k5},
+        "elements_per_count": {"clique4": inst[4]["elements"], "clique5": inst[5]["elements"]},
+        "roofline": {"bound": "hbm", "kernel": "gpm_persistent<clique> (5-clique launch)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": b5},
+    }
+    return out, g, inst
+
+
+def run_triangle(args, ctx, torch):
+    from paper_2112_09761_amd import synth
+    g = synth.workload_er_triangle(1)
+    gid = ctx.load(g)
+    ctx.graph_info(gid)
+    ctx.set_option("count_elements", 1)
+    ctx.count(gid, "triangle")
+    inst = ctx.stats()
+    ctx.set_option("count_elements", 0)
+    for _ in range(args.warmup):
+        ctx.count(gid, "triangle")
+    torch.cuda.synchronize()
+    ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c = ctx.count(gid, "triangle")
+        ms.append(ctx.stats()["kernel_ms"])
+    dt = time.perf_counter() - t0
+    return {"metric": "triangle count time (ER G(2000, 0.01))", "value": dt * 1e3 / args.steps,
+            "unit": "ms/count", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "er_2000_p0.01_triangle"}, "count": c,
+            "kernel_ms": statistics.mean(ms), "elements": inst["elements"]}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the counting "
+              f"path needs no collective and is measured on one MI355X.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2112_09761_amd import gpm
+    torch.cuda.set_device(0)
+    ctx = gpm.Context(0, torch.cuda.current_stream())
+    for kv in args.option:
+        k, v = kv.split("=")
+        ctx.set_option(k, int(v))
+    if args.workload == "clique":
+        out, g, inst = run_clique(args, ctx, torch)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"], c4 = cpu_baseline_clique4(g, inst[4]["elements"])
+            out["cpu_baseline_count_matches"] = c4 == out["counts"]["clique4"]
+        else:
+            out["cpu_baseline"] = None
+    elif args.workload == "triangle":
+        out = run_triangle(args, ctx, torch)
+    else:
+        from paper_2112_09761_amd import bench_workloads
+        out = bench_workloads.run(args, ctx, torch)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

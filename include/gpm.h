@@ -92,6 +92,7 @@ typedef struct {
     int64_t elements;        /* intersected elements (only when the option
                                 "count_elements" is 1; else -1)               */
     int64_t list_fetches;    /* neighbour-list reads (same option)            */
+    int64_t frontier_written;/* frontier elements stored (same option)        */
     int64_t frontier_bytes;  /* device frontier buffer size                  */
     int32_t launches;        /* kernel launches of the call                   */
     int32_t variant;         /* kernel variant the autotuner chose            */

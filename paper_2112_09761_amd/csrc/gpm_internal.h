@@ -2,6 +2,8 @@
 // libgpm (never exposed through include/gpm.h).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace gpm {
@@ -47,13 +49,17 @@ enum JobKind : int32_t {
   kJobDfs = 2,         // generic plan-driven DFS on a symmetric graph
   kJobEdgeTri = 3,     // per-edge triangle counts and the 4-motif edge terms
   kJobVertexDeg = 4,   // per-vertex degree terms
+  kJobCliqueLgs = 5,   // k-clique (k = 3..5) by local graph search with bitmaps
 };
 
 constexpr uint32_t kKindClique = 1u << kJobClique;
 constexpr uint32_t kKindDfs = 1u << kJobDfs;
 constexpr uint32_t kKindEdgeTri = 1u << kJobEdgeTri;
 constexpr uint32_t kKindVertexDeg = 1u << kJobVertexDeg;
-constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg;
+constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
+constexpr uint32_t kKindAll =
+    kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg | kKindCliqueLgs;
+constexpr int kLgsMaxVertices = 1024;   // local graphs handled by the bitmap kernel
 
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
 // root tasks) triple with its own result slot.
@@ -79,15 +85,23 @@ struct KernelArgs {
   int32_t n_jobs;
   int32_t lds_cap;                 // clique LDS tile (elements per set)
   const Plan* plans;
-  const int64_t* queue_begin;      // [kQueues + 1] chunk ranges of the queues
+  const int64_t* queue_begin;      // [kQueues + 1]; [kQueues] = chunk count
   unsigned long long* queue_cnt;   // [kQueues * kQueueStride]
   unsigned long long* results;     // [slots * kResultFields]
   unsigned long long* counters;    // [4]: elements, list fetches (instrumented)
   int32_t* fbuf;                   // HBM frontier buffers
   int64_t wave_stride;             // int32 words of fbuf per wave
   int32_t lds_words;               // int32 words of dynamic LDS per wave
+  int32_t lgs_tile;                // local graphs up to this size use LDS
   int32_t pad;
 };
+
+// Local-graph tile of T vertices: L[T] | P[T + 1] | R[T * ceil(T / 64)] uint64,
+// sizes in int32 words (R starts 8-byte aligned).
+__host__ __device__ inline int64_t lgs_rows_offset(int64_t T) { return (2 * T + 2) & ~int64_t(1); }
+__host__ __device__ inline int64_t lgs_tile_words(int64_t T) {
+  return lgs_rows_offset(T) + 2 * T * ((T + 63) / 64);
+}
 
 // Host-side launcher (kernels.hip).  Returns a hipError_t as int.
 int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a,

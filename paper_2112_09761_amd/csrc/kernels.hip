@@ -97,9 +97,12 @@ __device__ __forceinline__ int32_t upper_bound(const T* a, int32_t n, int32_t ke
   return base + (a[base] <= key ? 1 : 0);
 }
 
+// Instrumented builds only (CE = true): the method's own work, counted the
+// same way in every lane (summed over the wave, then divided by 64).
 struct ElemCounter {
-  uint64_t elems = 0;
-  uint64_t fetches = 0;
+  uint64_t elems = 0;     // sum over set operations of the bounded operand lengths
+  uint64_t fetches = 0;   // neighbour-list reads
+  uint64_t written = 0;   // frontier elements stored
 };
 
 // ---------------------------------------------------------------------------
@@ -146,7 +149,7 @@ __device__ __forceinline__ uint32_t intersect_count(const TA* A, int32_t na, con
 
 // Sum over w in F of |F ∩ N+(w)|.  P is scratch of s + 1 ints.
 template <bool CE, typename TF, typename TP>
-__device__ __forceinline__ uint32_t clique_leaf(const int64_t* __restrict__ rp,
+__device__ __forceinline__ uint64_t clique_leaf(const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col,
                                                 const TF* F, int32_t s, TP* P,
                                                 ElemCounter& ec) {
@@ -170,7 +173,7 @@ __device__ __forceinline__ uint32_t clique_leaf(const int64_t* __restrict__ rp,
     ec.elems += (uint64_t)s * (uint64_t)s + (uint64_t)running;
     ec.fetches += (uint64_t)s;
   }
-  uint32_t c = 0;
+  uint64_t c = 0;
   for (int32_t tb = 0; tb < running; tb += 64) {
     int32_t t = tb + l;
     if (t < running) {
@@ -188,7 +191,7 @@ __device__ __forceinline__ uint32_t clique_leaf(const int64_t* __restrict__ rp,
 // U = N+(u) (LDS-staged or global), bufs: (k-3) sets of cap ints, P: cap+1,
 // st: 2*kMaxK ints of wave state.
 template <bool CE, typename TU, typename TB>
-__device__ __forceinline__ uint32_t clique_edge(const int64_t* __restrict__ rp,
+__device__ __forceinline__ uint64_t clique_edge(const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col, int k,
                                                 const TU* U, int32_t du, int32_t v,
                                                 TB* bufs, TB* P, int32_t cap,
@@ -202,11 +205,12 @@ __device__ __forceinline__ uint32_t clique_edge(const int64_t* __restrict__ rp,
   if (k == 3) return intersect_count(Nv, dv, U, du);
   TB* F2 = bufs;
   int32_t s2 = uni(intersect_store(Nv, dv, U, du, F2));
+  if (CE) ec.written += (uint64_t)s2;
   if (s2 < k - 2) return 0;
   if (k == 4) return clique_leaf<CE>(rp, col, F2, s2, P, ec);
 
   // depths 2 .. k-3 are iterated; F_{k-2} goes to the leaf
-  uint32_t c = 0;
+  uint64_t c = 0;
   int32_t* sz = st;
   int32_t* ix = st + kMaxK;
   int d = 2;
@@ -234,6 +238,7 @@ __device__ __forceinline__ uint32_t clique_edge(const int64_t* __restrict__ rp,
     if (CE) {
       ec.elems += (uint64_t)s + (uint64_t)dw;
       ec.fetches += 1;
+      ec.written += (uint64_t)sn;
     }
     if (d + 1 == k - 2) {
       if (sn >= 2) c += clique_leaf<CE>(rp, col, Fn, sn, P, ec);
@@ -249,6 +254,132 @@ __device__ __forceinline__ uint32_t clique_edge(const int64_t* __restrict__ rp,
     ++d;
     if (lane_id() == 0) { sz[d] = sn; ix[d] = 0; }
     wave_sync_mem();
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// k-clique by local graph search with bitmaps (Sec. 5.4 (2) and Sec. 6.2):
+// for a root u the search stays inside N+(u); its local DAG is stored as one
+// bitmap row per vertex of N+(u) (bit j of row i: N+(u)[i] -> N+(u)[j]).
+// Triangles, 4-cliques and 5-cliques rooted at u are then popcounts of
+// ANDed rows.  One wave per root vertex.
+// ---------------------------------------------------------------------------
+
+constexpr int kLgsMaxWords = 16;  // local graphs of up to 1024 vertices
+
+// position of the r-th (0-based) set bit of x (r < popcount(x))
+__device__ __forceinline__ int select64(uint64_t x, int r) {
+  int pos = 0;
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    int c = __popcll(x & ((1ull << s) - 1ull));
+    if (r >= c) {
+      r -= c;
+      x >>= s;
+      pos += s;
+    }
+  }
+  return pos;
+}
+
+// L: d ints, P: d + 1 ints, R: d * W uint64 (W = ceil(d / 64)).
+template <bool CE, typename TL, typename TP, typename TR>
+__device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col, int k,
+                                               int32_t u, int32_t d, TL* L, TP* P, TR* R,
+                                               ElemCounter& ec) {
+  const int l = lane_id();
+  const int32_t W = (d + 63) >> 6;
+  const int32_t* Nu = col + rp[u];
+  for (int32_t i = l; i < d; i += 64) L[i] = Nu[i];
+  for (int32_t i = l; i < d * W; i += 64) R[i] = 0ull;
+  // P[i] = sum of out-degrees of L[0..i)
+  int32_t running = 0;
+  for (int32_t ib = 0; ib < d; ib += 64) {
+    int32_t i = ib + l;
+    int32_t dd = 0;
+    if (i < d) {
+      int32_t v = Nu[i];
+      dd = (int32_t)(rp[v + 1] - rp[v]);
+    }
+    int32_t inc = wave_incl_scan(dd);
+    if (i < d) P[i + 1] = running + inc;
+    running += __shfl(inc, 63, 64);
+  }
+  if (l == 0) P[0] = 0;
+  wave_sync_mem();
+  const int32_t total = uni(running);
+  if (CE) {
+    ec.elems += (uint64_t)d * (uint64_t)d + (uint64_t)total;
+    ec.fetches += (uint64_t)d + 1;
+  }
+  // rows: N+(L[i]) ∩ N+(u), one element of N+(L[i]) per lane, membership by
+  // binary search in the staged list
+  for (int32_t tb = 0; tb < total; tb += 64) {
+    int32_t t = tb + l;
+    if (t < total) {
+      int32_t i = upper_bound(P + 1, d, t);
+      int32_t v = L[i];
+      int32_t x = col[rp[v] + (t - P[i])];
+      int32_t j = lower_bound(L, d, x);
+      if (j < d && L[j] == x) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
+    }
+  }
+  wave_sync_mem();
+  uint64_t c = 0;
+  if (k == 3) {
+    for (int32_t i = l; i < d * W; i += 64) c += (uint64_t)__popcll(R[i]);
+    return c;
+  }
+  // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
+  running = 0;
+  for (int32_t ib = 0; ib < d; ib += 64) {
+    int32_t i = ib + l;
+    int32_t pc = 0;
+    if (i < d)
+      for (int32_t w = 0; w < W; ++w) pc += __popcll(R[(size_t)i * W + w]);
+    int32_t inc = wave_incl_scan(pc);
+    if (i < d) P[i + 1] = running + inc;
+    running += __shfl(inc, 63, 64);
+  }
+  if (l == 0) P[0] = 0;
+  wave_sync_mem();
+  const int32_t pairs = uni(running);
+  for (int32_t tb = 0; tb < pairs; tb += 64) {
+    int32_t t = tb + l;
+    if (t >= pairs) continue;
+    int32_t i = upper_bound(P + 1, d, t);
+    int32_t r = t - P[i];
+    const TR* Ri = R + (size_t)i * W;
+    int32_t w = 0;
+    for (;; ++w) {
+      int32_t pc = __popcll(Ri[w]);
+      if (r < pc) break;
+      r -= pc;
+    }
+    const int32_t j = w * 64 + select64(Ri[w], r);
+    const TR* Rj = R + (size_t)j * W;
+    if (k == 4) {
+      for (int32_t x = 0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
+    } else {
+      uint64_t M[kLgsMaxWords];
+#pragma unroll
+      for (int x = 0; x < kLgsMaxWords; ++x) M[x] = (x < W) ? (Ri[x] & Rj[x]) : 0ull;
+#pragma unroll
+      for (int x = 0; x < kLgsMaxWords; ++x) {
+        if (x >= W) break;
+        uint64_t m = M[x];
+        while (m) {
+          int b = __builtin_ctzll(m);
+          m &= m - 1ull;
+          const TR* Rl = R + (size_t)(x * 64 + b) * W;
+#pragma unroll
+          for (int y = 0; y < kLgsMaxWords; ++y)
+            if (y < W) c += (uint64_t)__popcll(M[y] & Rl[y]);
+        }
+      }
+    }
   }
   return c;
 }
@@ -357,6 +488,7 @@ __device__ __forceinline__ int32_t dfs_level(const int64_t* __restrict__ rp,
   if (STORE) {
     wave_sync_mem();
     st.set[d] = out;
+    if (CE) ec.written += (uint64_t)total;
   }
   return total;
 }
@@ -371,14 +503,14 @@ __device__ __forceinline__ bool slice_excluded(const LevelPlan& L, const DfsStat
 // All matches extending the root (v0, v1): the depth-first walk over depths
 // 2 .. k-1; depth k-1 is count-only.  Wave-uniform control flow throughout.
 template <bool CE>
-__device__ uint32_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+__device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                              const Plan& P, int32_t v0, int32_t v1, int32_t* fb,
                              int32_t cap, DfsState& st, ElemCounter& ec) {
   const int k = P.k;
   st.v[0] = v0;
   st.v[1] = v1;
-  if (k == 3) return (uint32_t)dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, ec);
-  uint32_t c = 0;
+  if (k == 3) return (uint64_t)dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, ec);
+  uint64_t c = 0;
   int d = 2;
   {
     int32_t* out = fb + (size_t)(P.store_slot[2] < 0 ? 0 : P.store_slot[2]) * cap;
@@ -399,7 +531,7 @@ __device__ uint32_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
     }
     st.v[d] = x;
     if (d + 1 == k - 1) {
-      c += (uint32_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, ec);
+      c += (uint64_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, ec);
       ++st.ix[d];
       continue;
     }
@@ -420,11 +552,13 @@ __device__ __forceinline__ int64_t pop_chunk(unsigned long long* qcnt, const int
   for (int i = 0; i < kQueues; ++i) {
     int x = (home + i) & (kQueues - 1);
     if ((dead >> x) & 1u) continue;
-    int64_t limit = qbeg[x + 1] - qbeg[x];
+    // queue x owns chunks x, x + 8, x + 16, ... (qbeg[kQueues] = chunk count),
+    // so heavy and light regions of the task list reach every XCD
+    int64_t limit = (qbeg[kQueues] - x + kQueues - 1) / kQueues;
     unsigned long long c = 0;
     if (lane_id() == 0) c = atomicAdd(&qcnt[x * kQueueStride], 1ull);
     c = __shfl(c, 0, 64);
-    if ((int64_t)c < limit) return qbeg[x] + (int64_t)c;
+    if ((int64_t)c < limit) return (int64_t)c * kQueues + x;
     dead |= 1u << x;
   }
   return -1;
@@ -512,6 +646,25 @@ gpm_persistent(KernelArgs a) {
           acc[0] += clique_edge<CE>(rp, col, k, U, du, v, bufs, P, J.cap, st_words, ec);
         }
       }
+    } else if ((KINDS & kKindCliqueLgs) && kind == kJobCliqueLgs) {
+      nf = 1;
+      const int k = J.k;
+      for (int64_t t = t0; t < t1; ++t) {
+        int32_t u = uni(J.task_src[t]);
+        int32_t d = uni((int32_t)(rp[u + 1] - rp[u]));
+        // tile layout: L[T] | P[T + 1] | (pad to 8 B) | R[T * ceil(T / 64)] (uint64)
+        if (d <= a.lgs_tile) {
+          int32_t* L = my;
+          int32_t* Pp = L + a.lgs_tile;
+          unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, L, Pp, R, ec);
+        } else {
+          int32_t* L = fb;
+          int32_t* Pp = fb + J.cap;
+          unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, L, Pp, R, ec);
+        }
+      }
     } else if ((KINDS & kKindDfs) && kind == kJobDfs) {
       nf = 1;
       const Plan& P = a.plans[J.plan];
@@ -574,9 +727,11 @@ gpm_persistent(KernelArgs a) {
   if (CE) {
     uint64_t e = wave_sum_u64(ec.elems);
     uint64_t f = wave_sum_u64(ec.fetches);
+    uint64_t wr = wave_sum_u64(ec.written);
     if (lane_id() == 0) {
       atomicAdd(&a.counters[0], (unsigned long long)e / 64ull);
       atomicAdd(&a.counters[1], (unsigned long long)f / 64ull);
+      atomicAdd(&a.counters[2], (unsigned long long)wr / 64ull);
     }
   }
 }
@@ -605,6 +760,9 @@ static hipError_t launch_kinds(uint32_t kinds, const KernelArgs& a, int blocks, 
     case kKindDfs: return launch_t<kKindDfs, CE>(a, blocks, lds, s);
     case kKindEdgeTri: return launch_t<kKindEdgeTri, CE>(a, blocks, lds, s);
     case kKindVertexDeg: return launch_t<kKindVertexDeg, CE>(a, blocks, lds, s);
+    case kKindCliqueLgs: return launch_t<kKindCliqueLgs, CE>(a, blocks, lds, s);
+    case kKindCliqueLgs | kKindClique:
+      return launch_t<kKindCliqueLgs | kKindClique, CE>(a, blocks, lds, s);
     default: return launch_t<kKindAll, CE>(a, blocks, lds, s);
   }
 }

@@ -49,7 +49,17 @@ struct Graph {
   HostCSR host;             // symmetric graph, or the given DAG when dag_only
   GraphView sym;            // symmetric graph on device (unless dag_only)
   GraphView dag;            // degree-oriented DAG (lazy) or the given DAG
+  HostCSR dag_host;
   bool dag_ready = false;
+  // local-graph clique tasks: vertices by out-degree, descending (lazy)
+  int32_t* lgs_vtx = nullptr;
+  std::vector<int64_t> lgs_deg;     // out-degree of lgs order position i
+  bool lgs_ready = false;
+  // DAG edges whose source has more than kLgsMaxVertices out-neighbours
+  int32_t* big_src = nullptr;
+  int32_t* big_dst = nullptr;
+  int64_t n_big = 0;
+  int64_t lgs_max_used = -1;        // root size limit the lists were built for
   int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
   int32_t* lo_dst = nullptr;
   int64_t n_lo = 0;
@@ -63,6 +73,8 @@ struct QueryWork {
   int kind = GPM_QUERY_COUNT;
   int k = 0;
   int first_job = 0, n_jobs = 0;
+  int clique_first = 0, clique_n = 0;   // motifs(4): jobs of the 4-clique count
+  int cycle_first = 0, cycle_n = 0;     // motifs(4): jobs of the 4-cycle count
   uint64_t constant = 0;   // result known on the host (k <= 2, n < k, ...)
   bool has_constant = false;
   int64_t ticket = -1;
@@ -106,6 +118,7 @@ struct gpm_ctx {
   int64_t opt_clique_lds = 1, opt_rename = 0, opt_count_elements = 0, opt_autotune = 0;
   int64_t opt_lds_tile = 0, opt_max_batch = 4096, opt_serve_slots = kMaxSlots;
   int64_t opt_max_pending = 1 << 20;
+  int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
   gpm_stats stats{};
   Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
   // serving
@@ -154,6 +167,10 @@ static void free_view(GraphView& v) {
 static void free_graph(Graph& g) {
   free_view(g.sym);
   free_view(g.dag);
+  dev_free(g.lgs_vtx);
+  dev_free(g.big_src);
+  dev_free(g.big_dst);
+  g.lgs_vtx = g.big_src = g.big_dst = nullptr;
   dev_free(g.lo_src);
   dev_free(g.lo_dst);
   g.lo_src = g.lo_dst = nullptr;
@@ -212,15 +229,58 @@ static HostCSR orient_by_degree(const HostCSR& g) {
 
 static gpm_status ensure_dag(gpm_ctx* c, Graph& g) {
   if (g.dag_ready) return GPM_OK;
-  if (g.dag_only) {
-    gpm_status st = upload_view(c, g.host, true, &g.dag, &g.bytes);
+  if (g.dag_only) g.dag_host = g.host;
+  else g.dag_host = orient_by_degree(g.host);
+  gpm_status st = upload_view(c, g.dag_host, true, &g.dag, &g.bytes);
+  if (st) return st;
+  g.dag_ready = true;
+  return GPM_OK;
+}
+
+// Root vertices of the local-graph clique kernel, heaviest first so that the
+// long tasks start early; plus the DAG edges of vertices too large for it.
+static gpm_status ensure_lgs(gpm_ctx* c, Graph& g, int64_t lgs_max) {
+  if (g.lgs_ready && g.lgs_max_used == lgs_max) return GPM_OK;
+  if (g.lgs_ready) {
+    dev_free(g.lgs_vtx);
+    dev_free(g.big_src);
+    dev_free(g.big_dst);
+    g.lgs_vtx = g.big_src = g.big_dst = nullptr;
+    g.n_big = 0;
+    g.lgs_ready = false;
+  }
+  gpm_status st = ensure_dag(c, g);
+  if (st) return st;
+  const HostCSR& d = g.dag_host;
+  std::vector<int32_t> order;
+  for (int64_t u = 0; u < d.n; ++u)
+    if (d.rp[u + 1] - d.rp[u] >= 2) order.push_back((int32_t)u);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return d.rp[a + 1] - d.rp[a] > d.rp[b + 1] - d.rp[b];
+  });
+  g.lgs_deg.resize(order.size());
+  std::vector<int32_t> bs, bd;
+  for (size_t i = 0; i < order.size(); ++i) {
+    int64_t u = order[i];
+    g.lgs_deg[i] = d.rp[u + 1] - d.rp[u];
+    if (g.lgs_deg[i] > lgs_max)
+      for (int64_t p = d.rp[u]; p < d.rp[u + 1]; ++p) {
+        bs.push_back((int32_t)u);
+        bd.push_back(d.col[p]);
+      }
+  }
+  st = dev_upload(c, &g.lgs_vtx, order.data(), order.size());
+  if (st) return st;
+  g.n_big = (int64_t)bs.size();
+  if (g.n_big) {
+    st = dev_upload(c, &g.big_src, bs.data(), bs.size());
     if (st) return st;
-  } else {
-    HostCSR d = orient_by_degree(g.host);
-    gpm_status st = upload_view(c, d, true, &g.dag, &g.bytes);
+    st = dev_upload(c, &g.big_dst, bd.data(), bd.size());
     if (st) return st;
   }
-  g.dag_ready = true;
+  g.bytes += order.size() * 4 + bs.size() * 8;
+  g.lgs_ready = true;
+  g.lgs_max_used = lgs_max;
   return GPM_OK;
 }
 
@@ -302,6 +362,43 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     J.n_tasks = g.dag.nnz;
     J.k = p.k;
     J.cap = (int32_t)cap;
+    const bool lgs = c->opt_clique_lds && c->opt_clique_algo != 1 && p.k <= 5;
+    if (lgs) {
+      // local graph search with bitmaps for roots with at most
+      // kLgsMaxVertices out-neighbours; larger roots take the edge kernel
+      st = ensure_lgs(c, g, c->opt_lgs_max);
+      if (st) return st;
+      const auto& dg = g.lgs_deg;  // descending
+      // first root with out-degree <= lgs_max, first root with out-degree < k-1
+      int64_t lo = std::lower_bound(dg.begin(), dg.end(), c->opt_lgs_max,
+                                    [](int64_t x, int64_t y) { return x > y; }) - dg.begin();
+      int64_t hi = std::upper_bound(dg.begin(), dg.end(), (int64_t)(p.k - 1),
+                                    [](int64_t x, int64_t y) { return x > y; }) - dg.begin();
+      Job L = J;
+      L.kind = kJobCliqueLgs;
+      L.vertex_tasks = 1;
+      L.task_src = g.lgs_vtx + lo;
+      L.task_dst = nullptr;
+      L.n_tasks = std::max<int64_t>(hi - lo, 0);
+      L.chunk = c->opt_chunk > 0 ? (int)c->opt_chunk : 2;
+      L.cap = (int32_t)std::min<int64_t>(cap, c->opt_lgs_max);
+      js.jobs.push_back(L);
+      js.need_words.push_back(0);  // sized at launch from the LDS tile
+      qw.n_jobs += 1;
+      if (g.n_big) {
+        Job B = J;
+        B.kind = kJobClique;
+        B.task_src = g.big_src;
+        B.task_dst = g.big_dst;
+        B.n_tasks = g.n_big;
+        B.chunk = default_chunk(c, kJobClique);
+        B.lds_ok = 1;
+        js.jobs.push_back(B);
+        js.need_words.push_back(0);
+        qw.n_jobs += 1;
+      }
+      return GPM_OK;
+    }
     if (c->opt_clique_lds) {
       J.kind = kJobClique;
       J.chunk = default_chunk(c, kJobClique);
@@ -406,35 +503,17 @@ static gpm_status add_motif_jobs(gpm_ctx* c, Graph& g, int k, JobPlanSet& js, Qu
     gpm_pattern p;
     QueryWork tmp;
     gpm_pattern_clique(4, &p);
+    qw.clique_first = (int)js.jobs.size() - qw.first_job;
     st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
     if (st) return st;
-    if (tmp.has_constant) {  // no job was added: add an empty placeholder
-      Job J{};
-      J.kind = kJobVertexDeg;
-      J.rp = g.sym.rp;
-      J.col = g.sym.col;
-      J.vertex_tasks = 1;
-      J.n_tasks = 0;
-      J.chunk = 1;
-      js.jobs.push_back(J);
-      js.need_words.push_back(0);
-    }
+    qw.clique_n = tmp.n_jobs;  // 0 when the count is known to be 0
     named("cycle4", &p);
     tmp = QueryWork{};
+    qw.cycle_first = (int)js.jobs.size() - qw.first_job;
     st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
     if (st) return st;
-    if (tmp.has_constant) {
-      Job J{};
-      J.kind = kJobVertexDeg;
-      J.rp = g.sym.rp;
-      J.col = g.sym.col;
-      J.vertex_tasks = 1;
-      J.n_tasks = 0;
-      J.chunk = 1;
-      js.jobs.push_back(J);
-      js.need_words.push_back(0);
-    }
-    qw.n_jobs += 2;
+    qw.cycle_n = tmp.n_jobs;
+    qw.n_jobs += qw.clique_n + qw.cycle_n;
   }
   return GPM_OK;
 }
@@ -447,8 +526,13 @@ static void finish_query(const QueryWork& qw, const unsigned long long* res, uin
     return;
   }
   auto slot = [&](int j, int f) { return (uint64_t)res[(size_t)(qw.first_job + j) * kResultFields + f]; };
+  auto sum0 = [&](int first, int n) {
+    uint64_t x = 0;
+    for (int j = 0; j < n; ++j) x += slot(first + j, 0);
+    return x;
+  };
   if (qw.kind == GPM_QUERY_COUNT) {
-    out[0] = slot(0, 0);
+    out[0] = sum0(0, qw.n_jobs);
     return;
   }
   const uint64_t sum_c2 = slot(0, 0), n_s3 = slot(0, 1);
@@ -460,7 +544,8 @@ static void finish_query(const QueryWork& qw, const unsigned long long* res, uin
     return;
   }
   // non-induced 4-vertex counts -> induced (unitriangular inclusion relation)
-  const uint64_t n_k4 = slot(2, 0), n_c4 = slot(3, 0);
+  const uint64_t n_k4 = sum0(qw.clique_first, qw.clique_n);
+  const uint64_t n_c4 = sum0(qw.cycle_first, qw.cycle_n);
   const uint64_t n_tt = two_tt / 2, n_p4 = pmid - 3 * T;
   const uint64_t i_k4 = n_k4;
   const uint64_t i_d = n_d - 6 * i_k4;
@@ -605,6 +690,16 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
         need[i] = (int64_t)(std::max((int)jobs[i].k - 3, 0) + 1) * jobs[i].cap + 1;
   }
 
+  // local-graph tile: roots with more out-neighbours than the tile keep
+  // their local graph in the wave's HBM region
+  int32_t lgs_T = 0;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].kind == kJobCliqueLgs) {
+      lgs_T = (int32_t)c->opt_lgs_tile;
+      if (jobs[i].cap > lgs_T) need[i] = std::max<int64_t>(need[i], lgs_tile_words(jobs[i].cap));
+    }
+  if (lgs_T) lds_words = std::max<int32_t>(lds_words, (int32_t)align_up((size_t)lgs_tile_words(lgs_T), 4));
+
   // frontier sizing (adaptive buffering): one region of `stride` words per wave
   int64_t stride = 0;
   for (int i = 0; i < nj; ++i) stride = std::max(stride, need[i]);
@@ -700,8 +795,10 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     a.counters = s.d_res + res_words + q_words;
     a.fbuf = fbytes ? s.d_fbuf : nullptr;
     a.wave_stride = stride;
-    a.lds_words = (L.kinds & kKindClique) ? lds_words : 0;
-    size_t lb = (L.kinds & kKindClique) ? lds_bytes : 0;
+    const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs)) != 0;
+    a.lds_words = uses_lds ? lds_words : 0;
+    a.lgs_tile = lgs_T;
+    size_t lb = uses_lds ? lds_bytes : 0;
     int e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
     if (e) return fail(c, GPM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
     ++n_launch;
@@ -729,6 +826,7 @@ static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
   if (c->opt_count_elements) {
     c->stats.elements = (int64_t)s.h_res[s.counters_off];
     c->stats.list_fetches = (int64_t)s.h_res[s.counters_off + 1];
+    c->stats.frontier_written = (int64_t)s.h_res[s.counters_off + 2];
   }
   return GPM_OK;
 }
@@ -742,6 +840,7 @@ static gpm_status run_sync(gpm_ctx* c, JobPlanSet& js, std::vector<QueryWork>& q
   c->stats = gpm_stats{};
   c->stats.elements = -1;
   c->stats.list_fetches = -1;
+  c->stats.frontier_written = -1;
   if (js.jobs.empty()) {
     for (size_t i = 0; i < qs.size(); ++i) finish_query(qs[i], nullptr, outs + 6 * i);
     c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -950,6 +1049,9 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "lds_tile") { if (v < 0 || v > 4096) return fail(c, GPM_E_INVAL, "lds_tile 0..4096"); c->opt_lds_tile = v; }
   else if (k == "rename") { if (v < -1 || v > 2) return fail(c, GPM_E_INVAL, "rename -1..2"); c->opt_rename = v; }
   else if (k == "count_elements") c->opt_count_elements = v != 0;
+  else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
+  else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
+  else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;
   else if (k == "max_batch") { if (v < 1) return fail(c, GPM_E_INVAL, "max_batch >= 1"); c->opt_max_batch = v; }
   else if (k == "serve_slots") { if (v < 1 || v > kMaxSlots) return fail(c, GPM_E_INVAL, "serve_slots 1..4"); c->opt_serve_slots = v; }

@@ -67,7 +67,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("tasks", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("chunk", ctypes.c_int64), ("elements", ctypes.c_int64),
-                ("list_fetches", ctypes.c_int64), ("frontier_bytes", ctypes.c_int64),
+                ("list_fetches", ctypes.c_int64), ("frontier_written", ctypes.c_int64),
+                ("frontier_bytes", ctypes.c_int64),
                 ("launches", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
     def as_dict(self):

@@ -159,14 +159,32 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
     try:
         for opt, vals in [("chunk", [1, 3, 64]), ("waves_per_cu", [1, 4, 32]),
                           ("lds_tile", [32, 64, 4096]), ("clique_lds", [0]),
-                          ("granularity", [1])]:
+                          ("granularity", [1]), ("clique_algo", [1, 2]),
+                          ("lgs_tile", [64, 128]), ("lgs_max", [64, 100])]:
             for v in vals:
                 ctx.set_option(opt, v)
                 for n, e in exp.items():
                     assert ctx.count(gid, n, V) == e, (opt, v, n)
             ctx.set_option(opt, {"chunk": 0, "waves_per_cu": 0, "lds_tile": 0,
-                                 "clique_lds": 1, "granularity": 0}[opt])
+                                 "clique_lds": 1, "granularity": 0, "clique_algo": 0,
+                                 "lgs_tile": 256, "lgs_max": 1024}[opt])
     finally:
+        ctx.unload(gid)
+
+
+def test_large_roots_take_edge_kernel(ctx, oracle):
+    """Roots above the local-graph limit go to the edge-parallel kernel; the
+    split must not change any count (K_n has out-degrees up to n - 1)."""
+    g = synth.disjoint_union(synth.complete(150), synth.rmat(10, 8, seed=801))
+    gid = ctx.load(g)
+    try:
+        for lim in (64, 100, 1024):
+            ctx.set_option("lgs_max", lim)
+            for k in (3, 4, 5):
+                assert ctx.count(gid, synth_clique(k)) == oracle.cliques(g, k), (lim, k)
+        assert ctx.motifs(gid, 4) == oracle.motifs4(g)
+    finally:
+        ctx.set_option("lgs_max", 1024)
         ctx.unload(gid)
 
 
