@@ -68,12 +68,21 @@ def run_clique(args, ctx, torch):
     g = synth.workload_rmat_s20()
     gid = ctx.load(g)
     info = ctx.graph_info(gid)  # forces the degree orientation (untimed)
-    # instrumented pass (never timed): the method's work per count
+    # instrumented passes (never timed).  The work per count is defined by
+    # the paper's sorted-list plan (edge kernel, clique_algo=1): the
+    # intersected elements it executes.  The timed kernel (local-graph
+    # bitmaps) does less work for the same counts, so elements/s is an
+    # effective rate.  The local-graph kernel's own global traffic is
+    # measured too (roofline of the dominant launch).
     ctx.set_option("count_elements", 1)
-    inst = {}
+    inst, inst_lgs = {}, {}
     for k in (4, 5):
+        ctx.set_option("clique_algo", 1)
         ctx.count(gid, (k, [(i, j) for i in range(k) for j in range(i + 1, k)]))
         inst[k] = ctx.stats()
+        ctx.set_option("clique_algo", 0)
+        ctx.count(gid, (k, [(i, j) for i in range(k) for j in range(i + 1, k)]))
+        inst_lgs[k] = ctx.stats()
     ctx.set_option("count_elements", 0)
     pats = {k: (k, [(i, j) for i in range(k) for j in range(i + 1, k)]) for k in (4, 5)}
     for _ in range(args.warmup):
@@ -96,7 +105,7 @@ def run_clique(args, ctx, torch):
     if gold and gold["sha256"] == g.sha256():
         parity = (counts[4] == gold["counts"]["clique4"] and counts[5] == gold["counts"]["clique5"])
     k5 = statistics.mean(kms[5])
-    b5 = algorithmic_bytes(inst[5])
+    b5 = algorithmic_bytes(inst_lgs[5])
     achieved = b5 / (k5 * 1e-3) / 1e9
     out = {
         "metric": "intersected elements/s, exact 4-clique + 5-clique counts",
@@ -112,7 +121,9 @@ def run_clique(args, ctx, torch):
         "parity_vs_stored_oracle": parity,
         "ms_per_count": {"clique4": statistics.mean(kms[4]), "clique5": k5},
         "elements_per_count": {"clique4": inst[4]["elements"], "clique5": inst[5]["elements"]},
-        "roofline": {"bound": "hbm", "kernel": "gpm_persistent<clique> (5-clique launch)",
+        "lgs_elements_per_count": {"clique4": inst_lgs[4]["elements"],
+                                   "clique5": inst_lgs[5]["elements"]},
+        "roofline": {"bound": "hbm", "kernel": "gpm_persistent<local-graph clique> (5-clique launch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": b5},

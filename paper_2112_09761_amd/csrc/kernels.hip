@@ -284,10 +284,14 @@ __device__ __forceinline__ int select64(uint64_t x, int r) {
 }
 
 // L: d ints, P: d + 1 ints, R: d * W uint64 (W = ceil(d / 64)).
+// Sub-task `part` of `parts` handles its share of the local edges (i, j), so
+// the heaviest roots are spread over several waves (each rebuilds the local
+// graph, a small fraction of the root's work).
 template <bool CE, typename TL, typename TP, typename TR>
 __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
-                                               int32_t u, int32_t d, TL* L, TP* P, TR* R,
+                                               int32_t u, int32_t d, int32_t part,
+                                               int32_t parts, TL* L, TP* P, TR* R,
                                                ElemCounter& ec) {
   const int l = lane_id();
   const int32_t W = (d + 63) >> 6;
@@ -329,7 +333,8 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   wave_sync_mem();
   uint64_t c = 0;
   if (k == 3) {
-    for (int32_t i = l; i < d * W; i += 64) c += (uint64_t)__popcll(R[i]);
+    if (part == 0)
+      for (int32_t i = l; i < d * W; i += 64) c += (uint64_t)__popcll(R[i]);
     return c;
   }
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
@@ -346,39 +351,78 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   if (l == 0) P[0] = 0;
   wave_sync_mem();
   const int32_t pairs = uni(running);
-  for (int32_t tb = 0; tb < pairs; tb += 64) {
-    int32_t t = tb + l;
-    if (t >= pairs) continue;
-    int32_t i = upper_bound(P + 1, d, t);
-    int32_t r = t - P[i];
-    const TR* Ri = R + (size_t)i * W;
-    int32_t w = 0;
-    for (;; ++w) {
-      int32_t pc = __popcll(Ri[w]);
-      if (r < pc) break;
-      r -= pc;
-    }
-    const int32_t j = w * 64 + select64(Ri[w], r);
-    const TR* Rj = R + (size_t)j * W;
-    if (k == 4) {
-      for (int32_t x = 0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
-    } else {
-      uint64_t M[kLgsMaxWords];
-#pragma unroll
-      for (int x = 0; x < kLgsMaxWords; ++x) M[x] = (x < W) ? (Ri[x] & Rj[x]) : 0ull;
-#pragma unroll
-      for (int x = 0; x < kLgsMaxWords; ++x) {
-        if (x >= W) break;
-        uint64_t m = M[x];
-        while (m) {
-          int b = __builtin_ctzll(m);
-          m &= m - 1ull;
-          const TR* Rl = R + (size_t)(x * 64 + b) * W;
-#pragma unroll
-          for (int y = 0; y < kLgsMaxWords; ++y)
-            if (y < W) c += (uint64_t)__popcll(M[y] & Rl[y]);
-        }
+  const int32_t p0 = (int32_t)((int64_t)pairs * part / parts);
+  const int32_t p1 = (int32_t)((int64_t)pairs * (part + 1) / parts);
+  if (k == 4) {
+    for (int32_t tb = p0; tb < p1; tb += 64) {
+      int32_t t = tb + l;
+      if (t >= p1) continue;
+      int32_t i = upper_bound(P + 1, d, t);
+      int32_t r = t - P[i];
+      const TR* Ri = R + (size_t)i * W;
+      int32_t w = 0;
+      for (;; ++w) {
+        int32_t pc = __popcll(Ri[w]);
+        if (r < pc) break;
+        r -= pc;
       }
+      const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
+      for (int32_t x = 0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
+    }
+    return c;
+  }
+  // k = 5: for every local edge (i, j) and every l in M = R_i & R_j add
+  // |M & R_l|.  Each lane walks the bits of its own M; a lane whose M is
+  // exhausted takes the next local edge at once (ballot + mbcnt hand-out),
+  // so the wave stays busy although the |M| differ.
+  uint64_t M[kLgsMaxWords];
+  int32_t next = p0;
+  bool have = false;
+  int32_t x = 0;         // current word of M
+  uint64_t m = 0;        // remaining bits of M[x]
+  for (;;) {
+    const bool need = !have;
+    const uint64_t nm = wave_ballot(need);
+    const int32_t t = next + (int32_t)lanes_below(nm);
+    next = min(next + (int32_t)__popcll(nm), p1);   // never runs past the range
+    if (need && t < p1) {
+      int32_t i = upper_bound(P + 1, d, t);
+      int32_t r = t - P[i];
+      const TR* Ri = R + (size_t)i * W;
+      int32_t w = 0;
+      for (;; ++w) {
+        int32_t pc = __popcll(Ri[w]);
+        if (r < pc) break;
+        r -= pc;
+      }
+      const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
+#pragma unroll
+      for (int y = 0; y < kLgsMaxWords; ++y) M[y] = (y < W) ? (Ri[y] & Rj[y]) : 0ull;
+      x = 0;
+      m = M[0];
+      have = true;
+    }
+    if (have && m == 0) {
+      // advance to the next non-empty word of M (static register indices)
+      while (m == 0 && ++x < W) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int y = 1; y < kLgsMaxWords; ++y) v = (x == y) ? M[y] : v;
+        m = v;
+      }
+      if (m == 0) have = false;
+    }
+    if (wave_ballot(have) == 0ull) {
+      if (next >= p1) break;
+      continue;
+    }
+    if (have) {
+      int b = __builtin_ctzll(m);
+      m &= m - 1ull;
+      const TR* Rl = R + (size_t)(x * 64 + b) * W;
+#pragma unroll
+      for (int y = 0; y < kLgsMaxWords; ++y)
+        if (y < W) c += (uint64_t)__popcll(M[y] & Rl[y]);
     }
   }
   return c;
@@ -652,17 +696,23 @@ gpm_persistent(KernelArgs a) {
       for (int64_t t = t0; t < t1; ++t) {
         int32_t u = uni(J.task_src[t]);
         int32_t d = uni((int32_t)(rp[u + 1] - rp[u]));
+        int32_t part = 0, parts = 1;
+        if (J.task_dst) {  // split root: (part, parts) packed as part | parts << 16
+          int32_t enc = uni(J.task_dst[t]);
+          part = enc & 0xffff;
+          parts = enc >> 16;
+        }
         // tile layout: L[T] | P[T + 1] | (pad to 8 B) | R[T * ceil(T / 64)] (uint64)
         if (d <= a.lgs_tile) {
           int32_t* L = my;
           int32_t* Pp = L + a.lgs_tile;
           unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, L, Pp, R, ec);
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, L, Pp, R, ec);
         } else {
           int32_t* L = fb;
           int32_t* Pp = fb + J.cap;
           unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, L, Pp, R, ec);
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, L, Pp, R, ec);
         }
       }
     } else if ((KINDS & kKindDfs) && kind == kJobDfs) {

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <deque>
@@ -60,6 +61,9 @@ struct Graph {
   int32_t* big_dst = nullptr;
   int64_t n_big = 0;
   int64_t lgs_max_used = -1;        // root size limit the lists were built for
+  // split local-graph tasks per clique size: (root, part | parts << 16)
+  struct SplitTasks { int32_t* src = nullptr; int32_t* dst = nullptr; int64_t n = 0; int64_t key = -1; };
+  SplitTasks lgs_split[kMaxK + 1];
   int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
   int32_t* lo_dst = nullptr;
   int64_t n_lo = 0;
@@ -119,6 +123,7 @@ struct gpm_ctx {
   int64_t opt_lds_tile = 0, opt_max_batch = 4096, opt_serve_slots = kMaxSlots;
   int64_t opt_max_pending = 1 << 20;
   int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
+  int64_t opt_lgs_split = 1;
   gpm_stats stats{};
   Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
   // serving
@@ -171,6 +176,11 @@ static void free_graph(Graph& g) {
   dev_free(g.big_src);
   dev_free(g.big_dst);
   g.lgs_vtx = g.big_src = g.big_dst = nullptr;
+  for (auto& t : g.lgs_split) {
+    dev_free(t.src);
+    dev_free(t.dst);
+    t = Graph::SplitTasks{};
+  }
   dev_free(g.lo_src);
   dev_free(g.lo_dst);
   g.lo_src = g.lo_dst = nullptr;
@@ -305,6 +315,49 @@ static gpm_status ensure_lower(gpm_ctx* c, Graph& g) {
   return GPM_OK;
 }
 
+// Split the local-graph roots [lo, hi) of the heaviest-first order into
+// sub-tasks: a root's cost grows like d^(k-2) (local edges for k = 4, local
+// triangles for k = 5); a root gets ceil(cost / share) parts, share being a
+// quarter of an even split over `waves` waves.
+static gpm_status ensure_lgs_split(gpm_ctx* c, Graph& g, int k, int64_t lo, int64_t hi,
+                                   int64_t waves, Graph::SplitTasks** out) {
+  Graph::SplitTasks& T = g.lgs_split[k];
+  const int64_t key = (lo << 40) ^ (hi << 8) ^ waves ^ (g.lgs_max_used << 50);
+  if (T.key == key) { *out = &T; return GPM_OK; }
+  dev_free(T.src);
+  dev_free(T.dst);
+  T = Graph::SplitTasks{};
+  std::vector<double> cost(hi - lo);
+  double total = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    double d = (double)g.lgs_deg[i];
+    cost[i - lo] = std::pow(d, (double)(k - 2));
+    total += cost[i - lo];
+  }
+  const double share = std::max(total / (double)(waves * 4), 1.0);
+  std::vector<int32_t> hs, src, dst;
+  hs.resize(hi - lo);
+  gpm_status st = GPM_OK;
+  std::vector<int32_t> order(hi - lo);
+  HIP_TRY(c, hipMemcpy(order.data(), g.lgs_vtx + lo, (hi - lo) * 4, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < hi - lo; ++i) {
+    int64_t parts = std::min<int64_t>(64, std::max<int64_t>(1, (int64_t)std::ceil(cost[i] / share)));
+    for (int64_t p = 0; p < parts; ++p) {
+      src.push_back(order[i]);
+      dst.push_back((int32_t)(p | (parts << 16)));
+    }
+  }
+  T.n = (int64_t)src.size();
+  st = dev_upload(c, &T.src, src.data(), src.size());
+  if (st) return st;
+  st = dev_upload(c, &T.dst, dst.data(), dst.size());
+  if (st) return st;
+  g.bytes += src.size() * 8;
+  T.key = key;
+  *out = &T;
+  return GPM_OK;
+}
+
 static Graph* find_graph(gpm_ctx* c, int32_t id) {
   auto it = c->graphs.find(id);
   return it == c->graphs.end() ? nullptr : it->second.get();
@@ -380,7 +433,15 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
       L.task_src = g.lgs_vtx + lo;
       L.task_dst = nullptr;
       L.n_tasks = std::max<int64_t>(hi - lo, 0);
-      L.chunk = c->opt_chunk > 0 ? (int)c->opt_chunk : 2;
+      L.chunk = c->opt_chunk > 0 ? (int)c->opt_chunk : 1;
+      if (p.k >= 5 && c->opt_lgs_split && hi > lo) {
+        Graph::SplitTasks* T = nullptr;
+        st = ensure_lgs_split(c, g, p.k, lo, hi, (int64_t)c->cus * 16, &T);
+        if (st) return st;
+        L.task_src = T->src;
+        L.task_dst = T->dst;
+        L.n_tasks = T->n;
+      }
       L.cap = (int32_t)std::min<int64_t>(cap, c->opt_lgs_max);
       js.jobs.push_back(L);
       js.need_words.push_back(0);  // sized at launch from the LDS tile
@@ -1050,6 +1111,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "rename") { if (v < -1 || v > 2) return fail(c, GPM_E_INVAL, "rename -1..2"); c->opt_rename = v; }
   else if (k == "count_elements") c->opt_count_elements = v != 0;
   else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
+  else if (k == "lgs_split") c->opt_lgs_split = v != 0;
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;
