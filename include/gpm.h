@@ -126,8 +126,18 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *   "setop"           0 auto, 1 binary search, 2 merge path
  *   "clique_lds"      1 = clique kernel keeps frontiers in LDS (default),
  *                     0 = force the generic kernel with HBM frontiers
- *   "rename"          non-clique patterns: 0 ids as given, 1 rename by
- *                     ascending degree, 2 by descending degree, -1 auto
+ *   "rename"          non-clique patterns run on a copy relabelled by
+ *                     ascending (degree, id) (1, default) or on the ids as
+ *                     given (0); counts are identical either way
+ *   "clique_algo"     0 auto (local-graph bitmaps for cliques up to 5
+ *                     vertices), 1 sorted-list edge kernel, 2 bitmaps
+ *   "lgs_tile"        local graphs up to this many vertices stay in LDS
+ *                     (64..256; larger ones use HBM rows)
+ *   "lgs_max"         roots with more out-neighbours (64..1024) use the
+ *                     edge kernel
+ *   "lgs_split"       1 = split the heaviest 5-clique roots across waves
+ *   "leaf_cap"        generic DFS: last-level candidates whose leaf set is
+ *                     at most this long are counted one per lane (0 = off)
  *   "count_elements"  1 = instrumented kernels count intersected elements
  *                     (slower; never used for timing)
  *   "autotune"        1 = time candidate configurations on first use of a

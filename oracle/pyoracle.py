@@ -40,29 +40,38 @@ def clique(k):
     return (k, [(i, j) for i in range(k) for j in range(i + 1, k)])
 
 
+def load(path):
+    """Load an oracle library from `path` with its argument types declared."""
+    L = ctypes.CDLL(path)
+    _declare(L)
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         path = _build.LIB
         if not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(path)
-        L.orc_pattern_aut.argtypes = [ctypes.c_int, P_I32, ctypes.c_int, P_U64]
-        for name in ("orc_count_subsets", "orc_count_embed"):
-            f = getattr(L, name)
-            f.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int, P_I32,
-                          ctypes.c_int, ctypes.c_int, P_U64]
-        L.orc_triangles.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
-                                    P_U64, P_U64, P_U64]
-        L.orc_cliques.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
-                                  ctypes.c_int, P_U64]
-        L.orc_cycle4.argtypes = [ctypes.c_int64, P_I64, P_I32, P_U64]
-        for name in ("orc_nonind4", "orc_motifs3", "orc_motifs4"):
-            getattr(L, name).argtypes = [ctypes.c_int64, P_I64, P_I32,
-                                         ctypes.c_int, P_U64]
-        L.orc_num_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def _declare(L):
+    L.orc_pattern_aut.argtypes = [ctypes.c_int, P_I32, ctypes.c_int, P_U64]
+    for name in ("orc_count_subsets", "orc_count_embed"):
+        f = getattr(L, name)
+        f.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int, P_I32,
+                      ctypes.c_int, ctypes.c_int, P_U64]
+    L.orc_triangles.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
+                                P_U64, P_U64, P_U64]
+    L.orc_cliques.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
+                              ctypes.c_int, P_U64]
+    L.orc_cycle4.argtypes = [ctypes.c_int64, P_I64, P_I32, P_U64]
+    for name in ("orc_nonind4", "orc_motifs3", "orc_motifs4"):
+        getattr(L, name).argtypes = [ctypes.c_int64, P_I64, P_I32,
+                                     ctypes.c_int, P_U64]
+    L.orc_num_threads.restype = ctypes.c_int
 
 
 class OracleError(RuntimeError):

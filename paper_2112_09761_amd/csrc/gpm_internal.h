@@ -77,6 +77,8 @@ struct Job {
   int32_t vertex_tasks;    // 1: tasks are root vertices
   int32_t cap;             // frontier capacity in elements (max set size)
   int32_t lds_ok;          // clique job: sets fit the LDS tile
+  int32_t leaf_cap;        // DFS job: lane-per-candidate leaves up to this size
+  int32_t pad;
 };
 
 struct KernelArgs {

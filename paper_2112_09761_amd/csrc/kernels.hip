@@ -544,12 +544,128 @@ __device__ __forceinline__ bool slice_excluded(const LevelPlan& L, const DfsStat
   return false;
 }
 
+// Leaf count of depth d for THIS lane's matched vertices (st.v differs per
+// lane), computed serially by the lane.  Returns false -- and counts nothing
+// -- when the bounded base set is longer than cap, so that the caller can
+// hand that candidate to the wave-wide set operation instead.
+template <bool CE>
+__device__ __forceinline__ bool leaf_serial(const int64_t* __restrict__ rp,
+                                            const int32_t* __restrict__ col,
+                                            const LevelPlan& L, const DfsState& st, int d,
+                                            int32_t cap, uint64_t& count, ElemCounter& ec) {
+  int32_t bound = INT_MAX;
+  for (int j = 0; j < d; ++j)
+    if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
+  const int32_t* base;
+  int32_t blen;
+  int base_i = -1;
+  if (L.base_buf >= 0) {
+    base = st.set[L.base_buf];
+    blen = st.sz[L.base_buf];
+  } else {
+    blen = INT_MAX;
+    base = nullptr;
+    for (int i = 0; i < L.n_int; ++i) {
+      int32_t vj = st.v[L.int_lv[i]];
+      int32_t len = (int32_t)(rp[vj + 1] - rp[vj]);
+      if (len < blen) { blen = len; base_i = i; base = col + rp[vj]; }
+    }
+  }
+  blen = lower_bound(base, blen, bound);
+  const int n_probe = L.n_int - (base_i >= 0 ? 1 : 0);
+  if (n_probe == 0 && L.n_sub == 0) {
+    int32_t c = blen;
+    for (int j = 0; j < d; ++j)
+      if ((L.excl_mask >> j) & 1)
+        if (st.v[j] < bound && member(base, blen, st.v[j])) --c;
+    count += (uint64_t)c;
+    if (CE) { ec.elems += (uint64_t)blen * 64; ec.fetches += 64; }
+    return true;
+  }
+  if (blen > cap) return false;
+  uint64_t c = 0;
+  for (int32_t i = 0; i < blen; ++i) {
+    const int32_t x = base[i];
+    bool keep = true;
+    for (int q = 0; q < L.n_int && keep; ++q) {
+      if (q == base_i) continue;
+      int32_t vj = st.v[L.int_lv[q]];
+      keep = member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int q = 0; q < L.n_sub && keep; ++q) {
+      int32_t vj = st.v[L.sub_lv[q]];
+      keep = !member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int j = 0; j < d && keep; ++j)
+      if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
+    c += keep ? 1u : 0u;
+  }
+  if (CE) {
+    uint64_t e = (uint64_t)blen;
+    for (int q = 0; q < L.n_int; ++q) {
+      if (q == base_i) continue;
+      int32_t vj = st.v[L.int_lv[q]];
+      e += (uint64_t)(rp[vj + 1] - rp[vj]);
+    }
+    for (int q = 0; q < L.n_sub; ++q) {
+      int32_t vj = st.v[L.sub_lv[q]];
+      e += (uint64_t)(rp[vj + 1] - rp[vj]);
+    }
+    ec.elems += e * 64;
+    ec.fetches += (uint64_t)(1 + n_probe + L.n_sub) * 64;
+  }
+  count += c;
+  return true;
+}
+
+// All leaves below the candidates of depth d = k-2: one candidate per lane
+// (leaf_serial); candidates whose leaf set exceeds cap are queued in defq
+// and counted with the wave-wide set operation.
+template <bool CE>
+__device__ uint64_t leaf_bulk(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              const Plan& P, int d, DfsState& st, int32_t cap, int32_t* defq,
+                              ElemCounter& ec) {
+  const LevelPlan& Ld = P.lv[d];
+  const LevelPlan& L = P.lv[d + 1];
+  const int32_t sz = uni(st.sz[d]);
+  const int32_t* set = st.set[d];
+  const int l = lane_id();
+  uint64_t c = 0;
+  for (int32_t ib = 0; ib < sz; ib += 64) {
+    const int32_t i = ib + l;
+    bool act = i < sz;
+    int32_t x = act ? set[i] : 0;
+    if (act && (Ld.flags & kLvSlice) && slice_excluded(Ld, st, d, x)) act = false;
+    bool defer = false;
+    if (act) {
+      st.v[d] = x;
+      uint64_t cnt = 0;
+      if (leaf_serial<CE>(rp, col, L, st, d + 1, cap, cnt, ec)) c += cnt;
+      else defer = true;
+    }
+    const uint64_t dm = wave_ballot(defer);
+    if (dm) {
+      if (defer) defq[lanes_below(dm)] = x;
+      wave_sync_mem();
+      const int nd = (int)__popcll(dm);
+      for (int q = 0; q < nd; ++q) {
+        st.v[d] = uni(defq[q]);
+        c += (uint64_t)dfs_level<false, CE>(rp, col, L, st, d + 1, nullptr, ec);
+      }
+      wave_sync_mem();
+    }
+  }
+  return c;
+}
+
 // All matches extending the root (v0, v1): the depth-first walk over depths
-// 2 .. k-1; depth k-1 is count-only.  Wave-uniform control flow throughout.
+// 2 .. k-1; depth k-1 is count-only.  Wave-uniform control flow throughout
+// except inside leaf_bulk, where each lane owns one last-level candidate.
 template <bool CE>
 __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                              const Plan& P, int32_t v0, int32_t v1, int32_t* fb,
-                             int32_t cap, DfsState& st, ElemCounter& ec) {
+                             int32_t cap, int32_t leaf_cap, DfsState& st, int32_t* defq,
+                             ElemCounter& ec) {
   const int k = P.k;
   st.v[0] = v0;
   st.v[1] = v1;
@@ -562,6 +678,22 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
     st.ix[2] = 0;
   }
   for (;;) {
+    if (d == k - 2) {
+      if (leaf_cap > 0) {
+        c += leaf_bulk<CE>(rp, col, P, d, st, leaf_cap, defq, ec);
+      } else {
+        for (int32_t i = 0; i < st.sz[d]; ++i) {
+          int32_t x = uni(st.set[d][i]);
+          if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) continue;
+          st.v[d] = x;
+          c += (uint64_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, ec);
+        }
+      }
+      if (d == 2) break;
+      --d;
+      ++st.ix[d];
+      continue;
+    }
     if (st.ix[d] >= st.sz[d]) {
       if (d == 2) break;
       --d;
@@ -574,11 +706,6 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
       continue;
     }
     st.v[d] = x;
-    if (d + 1 == k - 1) {
-      c += (uint64_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, ec);
-      ++st.ix[d];
-      continue;
-    }
     ++d;
     int32_t* out = fb + (size_t)(P.store_slot[d] < 0 ? 0 : P.store_slot[d]) * cap;
     st.sz[d] = uni(dfs_level<true, CE>(rp, col, P.lv[d], st, d, out, ec));
@@ -631,6 +758,7 @@ __global__ void __launch_bounds__(kWavesPerBlock * 64)
 gpm_persistent(KernelArgs a) {
   extern __shared__ int32_t lds[];
   __shared__ int32_t lds_state[kWavesPerBlock][2 * kMaxK];
+  __shared__ int32_t dfs_defq[(KINDS & kKindDfs) ? kWavesPerBlock : 1][64];
   const int w = threadIdx.x >> 6;
   int32_t* my = lds + (size_t)w * a.lds_words;
   int32_t* st_words = lds_state[w];
@@ -726,12 +854,14 @@ gpm_persistent(KernelArgs a) {
           int32_t end = P.root_bound ? uni(lower_bound(N0, d0, v0)) : d0;
           for (int32_t e = 0; e < end; ++e) {
             int32_t v1 = uni(N0[e]);
-            acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, st, ec);
+            acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, J.leaf_cap, st,
+                                   dfs_defq[w], ec);
           }
         } else {
           int32_t v0 = uni(J.task_src[t]);
           int32_t v1 = uni(J.task_dst[t]);
-          acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, st, ec);
+          acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, J.leaf_cap, st, dfs_defq[w],
+                                 ec);
         }
       }
     } else if ((KINDS & kKindEdgeTri) && kind == kJobEdgeTri) {

@@ -64,6 +64,14 @@ struct Graph {
   // split local-graph tasks per clique size: (root, part | parts << 16)
   struct SplitTasks { int32_t* src = nullptr; int32_t* dst = nullptr; int64_t n = 0; int64_t key = -1; };
   SplitTasks lgs_split[kMaxK + 1];
+  // relabelled copy for non-clique plans: ids by ascending (degree, id), so
+  // a symmetry bound v_j < v_i also bounds degree (lazy)
+  HostCSR ren_host;
+  GraphView ren;
+  int32_t* ren_lo_src = nullptr;
+  int32_t* ren_lo_dst = nullptr;
+  int64_t ren_n_lo = 0;
+  bool ren_ready = false;
   int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
   int32_t* lo_dst = nullptr;
   int64_t n_lo = 0;
@@ -119,11 +127,11 @@ struct gpm_ctx {
   int32_t next_graph = 1;
   // options
   int64_t opt_granularity = 0, opt_chunk = 0, opt_waves_per_cu = 0, opt_setop = 0;
-  int64_t opt_clique_lds = 1, opt_rename = 0, opt_count_elements = 0, opt_autotune = 0;
+  int64_t opt_clique_lds = 1, opt_rename = 1, opt_count_elements = 0, opt_autotune = 0;
   int64_t opt_lds_tile = 0, opt_max_batch = 4096, opt_serve_slots = kMaxSlots;
   int64_t opt_max_pending = 1 << 20;
   int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
-  int64_t opt_lgs_split = 1;
+  int64_t opt_lgs_split = 1, opt_leaf_cap = 128;
   gpm_stats stats{};
   Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
   // serving
@@ -171,6 +179,10 @@ static void free_view(GraphView& v) {
 
 static void free_graph(Graph& g) {
   free_view(g.sym);
+  free_view(g.ren);
+  dev_free(g.ren_lo_src);
+  dev_free(g.ren_lo_dst);
+  g.ren_lo_src = g.ren_lo_dst = nullptr;
   free_view(g.dag);
   dev_free(g.lgs_vtx);
   dev_free(g.big_src);
@@ -358,6 +370,58 @@ static gpm_status ensure_lgs_split(gpm_ctx* c, Graph& g, int k, int64_t lo, int6
   return GPM_OK;
 }
 
+static gpm_status lower_edges(gpm_ctx* c, const HostCSR& h, int32_t** src, int32_t** dst,
+                              int64_t* n, size_t* bytes) {
+  std::vector<int32_t> s, d;
+  s.reserve(h.rp[h.n] / 2);
+  d.reserve(h.rp[h.n] / 2);
+  for (int64_t u = 0; u < h.n; ++u)
+    for (int64_t p = h.rp[u]; p < h.rp[u + 1] && h.col[p] < u; ++p) {
+      s.push_back((int32_t)u);
+      d.push_back(h.col[p]);
+    }
+  *n = (int64_t)s.size();
+  gpm_status st = dev_upload(c, src, s.data(), s.size());
+  if (st) return st;
+  st = dev_upload(c, dst, d.data(), d.size());
+  if (st) return st;
+  *bytes += s.size() * 8;
+  return GPM_OK;
+}
+
+// Relabel by ascending (degree, id) rank (Sec. 3: the preprocessor may sort
+// and rename vertices by degree).  Counts are invariant under relabelling.
+static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
+  if (g.ren_ready) return GPM_OK;
+  const HostCSR& h = g.host;
+  std::vector<int32_t> order(h.n), rank(h.n);
+  for (int64_t u = 0; u < h.n; ++u) order[u] = (int32_t)u;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return h.rp[a + 1] - h.rp[a] < h.rp[b + 1] - h.rp[b];
+  });
+  for (int64_t r = 0; r < h.n; ++r) rank[order[r]] = (int32_t)r;
+  HostCSR& R = g.ren_host;
+  R.n = h.n;
+  R.rp.assign(h.n + 1, 0);
+  for (int64_t r = 0; r < h.n; ++r) {
+    int32_t u = order[r];
+    R.rp[r + 1] = R.rp[r] + (h.rp[u + 1] - h.rp[u]);
+  }
+  R.col.resize(h.col.size());
+  for (int64_t r = 0; r < h.n; ++r) {
+    int32_t u = order[r];
+    int64_t o = R.rp[r];
+    for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) R.col[o++] = rank[h.col[p]];
+    std::sort(R.col.begin() + R.rp[r], R.col.begin() + R.rp[r + 1]);
+  }
+  gpm_status st = upload_view(c, R, true, &g.ren, &g.bytes);
+  if (st) return st;
+  st = lower_edges(c, R, &g.ren_lo_src, &g.ren_lo_dst, &g.ren_n_lo, &g.bytes);
+  if (st) return st;
+  g.ren_ready = true;
+  return GPM_OK;
+}
+
 static Graph* find_graph(gpm_ctx* c, int32_t id) {
   auto it = c->graphs.find(id);
   return it == c->graphs.end() ? nullptr : it->second.get();
@@ -484,12 +548,19 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
   HostPlan hp;
   st = build_plan(p, mode, false, &hp, &err);
   if (st) return fail(c, st, err);
-  const int64_t cap = std::max<int64_t>(g.sym.max_deg, 1);
+  const bool ren = c->opt_rename != 0;
+  if (ren) {
+    st = ensure_ren(c, g);
+    if (st) return st;
+  }
+  GraphView& V = ren ? g.ren : g.sym;
+  const int64_t cap = std::max<int64_t>(V.max_deg, 1);
   Job J{};
   J.kind = kJobDfs;
+  J.leaf_cap = (int32_t)c->opt_leaf_cap;
   J.k = p.k;
-  J.rp = g.sym.rp;
-  J.col = g.sym.col;
+  J.rp = V.rp;
+  J.col = V.col;
   J.cap = (int32_t)cap;
   J.chunk = default_chunk(c, kJobDfs);
   J.plan = (int32_t)js.plans.size();
@@ -498,23 +569,30 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     J.vertex_tasks = 1;
     J.n_tasks = n;
   } else if (hp.plan.root_bound) {
-    st = ensure_lower(c, g);
-    if (st) return st;
-    J.task_src = g.lo_src;
-    J.task_dst = g.lo_dst;
-    J.n_tasks = g.n_lo;
+    if (ren) {
+      J.task_src = g.ren_lo_src;
+      J.task_dst = g.ren_lo_dst;
+      J.n_tasks = g.ren_n_lo;
+    } else {
+      st = ensure_lower(c, g);
+      if (st) return st;
+      J.task_src = g.lo_src;
+      J.task_dst = g.lo_dst;
+      J.n_tasks = g.n_lo;
+    }
   } else {
-    if (!g.sym.src) {
-      std::vector<int32_t> src(g.host.col.size());
+    if (!V.src) {
+      const HostCSR& H = ren ? g.ren_host : g.host;
+      std::vector<int32_t> src(H.col.size());
       for (int64_t u = 0; u < n; ++u)
-        for (int64_t q = g.host.rp[u]; q < g.host.rp[u + 1]; ++q) src[q] = (int32_t)u;
-      st = dev_upload(c, &g.sym.src, src.data(), src.size());
+        for (int64_t q = H.rp[u]; q < H.rp[u + 1]; ++q) src[q] = (int32_t)u;
+      st = dev_upload(c, &V.src, src.data(), src.size());
       if (st) return st;
       g.bytes += src.size() * 4;
     }
-    J.task_src = g.sym.src;
-    J.task_dst = g.sym.col;
-    J.n_tasks = g.sym.nnz;
+    J.task_src = V.src;
+    J.task_dst = V.col;
+    J.n_tasks = V.nnz;
   }
   js.plans.push_back(hp.plan);
   js.jobs.push_back(J);
@@ -1108,10 +1186,11 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "setop") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "setop 0..2"); c->opt_setop = v; }
   else if (k == "clique_lds") c->opt_clique_lds = v != 0;
   else if (k == "lds_tile") { if (v < 0 || v > 4096) return fail(c, GPM_E_INVAL, "lds_tile 0..4096"); c->opt_lds_tile = v; }
-  else if (k == "rename") { if (v < -1 || v > 2) return fail(c, GPM_E_INVAL, "rename -1..2"); c->opt_rename = v; }
+  else if (k == "rename") { if (v < 0 || v > 1) return fail(c, GPM_E_INVAL, "rename 0..1"); c->opt_rename = v; }
   else if (k == "count_elements") c->opt_count_elements = v != 0;
   else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
+  else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;

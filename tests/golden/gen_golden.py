@@ -31,7 +31,24 @@ WORKLOADS = {
 }
 
 
+def batch_golden():
+    """Induced 4-motif counts of the 256 graphs of the batched workload."""
+    recs = []
+    t0 = time.time()
+    for i in range(256):
+        g = synth.batch_graph(i)
+        t = time.time()
+        recs.append({"i": i, "n": g.n, "m": g.m, "sha256": g.sha256(),
+                     "motifs4": O.motifs4(g, 1), "seconds": round(time.time() - t, 2)})
+        print(i, g.n, g.m, recs[-1]["motifs4"], recs[-1]["seconds"], flush=True)
+    with open(os.path.join(HERE, "batch256_oracle.json"), "w") as f:
+        json.dump({"workload": "batch256", "oracle_threads": O.num_threads(),
+                   "seconds": round(time.time() - t0, 1), "graphs": recs}, f, indent=0)
+
+
 def main(name):
+    if name == "batch256":
+        return batch_golden()
     mk, items = WORKLOADS[name]
     g = mk()
     rec = {"workload": name, "generator": mk.__name__, "n": g.n, "m": g.m,
