@@ -93,6 +93,8 @@ typedef struct {
                                 "count_elements" is 1; else -1)               */
     int64_t list_fetches;    /* neighbour-list reads (same option)            */
     int64_t frontier_written;/* frontier elements stored (same option)        */
+    int64_t bitmap_words;    /* 64-bit AND+popcount word operations of the
+                                local-graph bitmap kernel (same option)      */
     int64_t frontier_bytes;  /* device frontier buffer size                  */
     int32_t launches;        /* kernel launches of the call                   */
     int32_t variant;         /* kernel variant the autotuner chose            */

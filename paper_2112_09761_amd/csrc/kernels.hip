@@ -103,6 +103,8 @@ struct ElemCounter {
   uint64_t elems = 0;     // sum over set operations of the bounded operand lengths
   uint64_t fetches = 0;   // neighbour-list reads
   uint64_t written = 0;   // frontier elements stored
+  uint64_t words = 0;     // bitmap word operations (AND + popcount of 64 bits),
+                          // counted per lane (summed, not divided by 64)
 };
 
 // ---------------------------------------------------------------------------
@@ -335,6 +337,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   if (k == 3) {
     if (part == 0)
       for (int32_t i = l; i < d * W; i += 64) c += (uint64_t)__popcll(R[i]);
+    if (CE && part == 0 && l == 0) ec.words += (uint64_t)d * W;
     return c;
   }
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
@@ -368,6 +371,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       }
       const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
       for (int32_t x = 0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
+      if (CE) ec.words += (uint64_t)W;
     }
     return c;
   }
@@ -398,6 +402,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
 #pragma unroll
       for (int y = 0; y < kLgsMaxWords; ++y) M[y] = (y < W) ? (Ri[y] & Rj[y]) : 0ull;
+      if (CE) ec.words += (uint64_t)W;
       x = 0;
       m = M[0];
       have = true;
@@ -423,6 +428,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
 #pragma unroll
       for (int y = 0; y < kLgsMaxWords; ++y)
         if (y < W) c += (uint64_t)__popcll(M[y] & Rl[y]);
+      if (CE) ec.words += (uint64_t)W;
     }
   }
   return c;
@@ -908,10 +914,12 @@ gpm_persistent(KernelArgs a) {
     uint64_t e = wave_sum_u64(ec.elems);
     uint64_t f = wave_sum_u64(ec.fetches);
     uint64_t wr = wave_sum_u64(ec.written);
+    uint64_t wo = wave_sum_u64(ec.words);
     if (lane_id() == 0) {
       atomicAdd(&a.counters[0], (unsigned long long)e / 64ull);
       atomicAdd(&a.counters[1], (unsigned long long)f / 64ull);
       atomicAdd(&a.counters[2], (unsigned long long)wr / 64ull);
+      atomicAdd(&a.counters[3], (unsigned long long)wo);
     }
   }
 }

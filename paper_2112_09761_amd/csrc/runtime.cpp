@@ -966,6 +966,7 @@ static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
     c->stats.elements = (int64_t)s.h_res[s.counters_off];
     c->stats.list_fetches = (int64_t)s.h_res[s.counters_off + 1];
     c->stats.frontier_written = (int64_t)s.h_res[s.counters_off + 2];
+    c->stats.bitmap_words = (int64_t)s.h_res[s.counters_off + 3];
   }
   return GPM_OK;
 }
@@ -980,6 +981,7 @@ static gpm_status run_sync(gpm_ctx* c, JobPlanSet& js, std::vector<QueryWork>& q
   c->stats.elements = -1;
   c->stats.list_fetches = -1;
   c->stats.frontier_written = -1;
+  c->stats.bitmap_words = -1;
   if (js.jobs.empty()) {
     for (size_t i = 0; i < qs.size(); ++i) finish_query(qs[i], nullptr, outs + 6 * i);
     c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

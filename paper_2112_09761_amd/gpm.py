@@ -68,6 +68,7 @@ class Stats(ctypes.Structure):
                 ("tasks", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("chunk", ctypes.c_int64), ("elements", ctypes.c_int64),
                 ("list_fetches", ctypes.c_int64), ("frontier_written", ctypes.c_int64),
+                ("bitmap_words", ctypes.c_int64),
                 ("frontier_bytes", ctypes.c_int64),
                 ("launches", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
