@@ -50,6 +50,7 @@ enum JobKind : int32_t {
   kJobEdgeTri = 3,     // per-edge triangle counts and the 4-motif edge terms
   kJobVertexDeg = 4,   // per-vertex degree terms
   kJobCliqueLgs = 5,   // k-clique (k = 3..5) by local graph search with bitmaps
+  kJobCycleWedge = 6,  // edge-induced 4-cycles by wedge aggregation
 };
 
 constexpr uint32_t kKindClique = 1u << kJobClique;
@@ -57,8 +58,9 @@ constexpr uint32_t kKindDfs = 1u << kJobDfs;
 constexpr uint32_t kKindEdgeTri = 1u << kJobEdgeTri;
 constexpr uint32_t kKindVertexDeg = 1u << kJobVertexDeg;
 constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
-constexpr uint32_t kKindAll =
-    kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg | kKindCliqueLgs;
+constexpr uint32_t kKindCycleWedge = 1u << kJobCycleWedge;
+constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg |
+                              kKindCliqueLgs | kKindCycleWedge;
 constexpr int kLgsMaxVertices = 1024;   // local graphs handled by the bitmap kernel
 
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
@@ -96,6 +98,8 @@ struct KernelArgs {
   int32_t lds_words;               // int32 words of dynamic LDS per wave
   int32_t lgs_tile;                // local graphs up to this size use LDS
   int32_t pad;
+  unsigned int* zbuf;              // per-wave counter arrays, zero between tasks
+  int64_t zstride;                 // words of zbuf per wave
 };
 
 // Local-graph tile of T vertices: L[T] | P[T + 1] | R[T * ceil(T / 64)] uint64,

@@ -435,6 +435,63 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
 }
 
 // ---------------------------------------------------------------------------
+// edge-induced 4-cycles by wedge aggregation (counting only; the paper's
+// counting-only pruning of Sec. 5.4 (1) applied to the 4-cycle).  On the
+// graph relabelled by ascending degree, every 4-cycle is counted once at its
+// largest vertex v together with the vertex w opposite v: with c_w the number
+// of wedges v-u-w (u, w < v), the root contributes sum_w C(c_w, 2).  Each wave
+// owns a zero-initialised counter array `cnt` (one word per vertex): pass 1
+// adds the wedges, pass 2 walks them again, takes each counter with an
+// atomic exchange (restoring zero) and adds C(c, 2) once per distinct w.
+// Sub-task (v, [a, b)) only counts endpoints w in [a, b), so a heavy root is
+// split across waves without any cross-task aggregation.
+// ---------------------------------------------------------------------------
+
+template <bool SECOND>
+__device__ __forceinline__ uint64_t wedge_pass(const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col,
+                                               const int32_t* Nlo, int32_t e, int32_t a,
+                                               int32_t b, unsigned int* cnt, int32_t* U,
+                                               int32_t* LO, int32_t* PF) {
+  const int l = lane_id();
+  uint64_t c = 0;
+  for (int32_t ub = 0; ub < e; ub += 64) {
+    const int32_t i = ub + l;
+    int32_t len = 0, lo = 0, u = 0;
+    if (i < e) {
+      u = Nlo[i];
+      const int32_t* Nu = col + rp[u];
+      const int32_t du = (int32_t)(rp[u + 1] - rp[u]);
+      lo = lower_bound(Nu, du, a);
+      len = lower_bound(Nu, du, b) - lo;
+    }
+    const int32_t incl = wave_incl_scan(len);
+    U[l] = u;
+    LO[l] = lo;
+    PF[l] = incl;
+    wave_sync_mem();
+    const int32_t tot = uni(__shfl(incl, 63, 64));
+    for (int32_t tb = 0; tb < tot; tb += 64) {
+      const int32_t t = tb + l;
+      if (t < tot) {
+        const int32_t o = upper_bound(PF, 64, t);
+        const int32_t r = t - (o > 0 ? PF[o - 1] : 0);
+        const int32_t uu = U[o];
+        const int32_t w = col[rp[uu] + LO[o] + r];
+        if (!SECOND) {
+          atomicAdd(&cnt[w], 1u);
+        } else {
+          const uint64_t x = (uint64_t)atomicExch(&cnt[w], 0u);
+          c += x * (x - (x ? 1 : 0)) / 2;
+        }
+      }
+    }
+    wave_sync_mem();
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
 // generic plan-driven DFS (Alg. 1 generalised by the plan table)
 // ---------------------------------------------------------------------------
 
@@ -765,6 +822,7 @@ gpm_persistent(KernelArgs a) {
   extern __shared__ int32_t lds[];
   __shared__ int32_t lds_state[kWavesPerBlock][2 * kMaxK];
   __shared__ int32_t dfs_defq[(KINDS & kKindDfs) ? kWavesPerBlock : 1][64];
+  __shared__ int32_t wedge_lds[(KINDS & kKindCycleWedge) ? kWavesPerBlock : 1][192];
   const int w = threadIdx.x >> 6;
   int32_t* my = lds + (size_t)w * a.lds_words;
   int32_t* st_words = lds_state[w];
@@ -847,6 +905,30 @@ gpm_persistent(KernelArgs a) {
           int32_t* Pp = fb + J.cap;
           unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
           acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, L, Pp, R, ec);
+        }
+      }
+    } else if ((KINDS & kKindCycleWedge) && kind == kJobCycleWedge) {
+      nf = 1;
+      unsigned int* cnt = a.zbuf + gw * a.zstride;
+      for (int64_t t = t0; t < t1; ++t) {
+        const int32_t v = uni(J.task_src[t]);
+        int32_t part = 0, parts = 1;
+        if (J.task_dst) {
+          const int32_t enc = uni(J.task_dst[t]);
+          part = enc & 0xffff;
+          parts = enc >> 16;
+        }
+        const int32_t* Nv = col + rp[v];
+        const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
+        const int32_t a0 = (int32_t)((int64_t)v * part / parts);
+        const int32_t b0 = (int32_t)((int64_t)v * (part + 1) / parts);
+        int32_t* U = wedge_lds[w];
+        wedge_pass<false>(rp, col, Nv, e, a0, b0, cnt, U, U + 64, U + 128);
+        // every counter update of pass 1 completes before pass 2 reads it
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        acc[0] += wedge_pass<true>(rp, col, Nv, e, a0, b0, cnt, U, U + 64, U + 128);
+        if (CE) {
+          ec.fetches += (uint64_t)e * 64;
         }
       }
     } else if ((KINDS & kKindDfs) && kind == kJobDfs) {
@@ -949,6 +1031,7 @@ static hipError_t launch_kinds(uint32_t kinds, const KernelArgs& a, int blocks, 
     case kKindEdgeTri: return launch_t<kKindEdgeTri, CE>(a, blocks, lds, s);
     case kKindVertexDeg: return launch_t<kKindVertexDeg, CE>(a, blocks, lds, s);
     case kKindCliqueLgs: return launch_t<kKindCliqueLgs, CE>(a, blocks, lds, s);
+    case kKindCycleWedge: return launch_t<kKindCycleWedge, CE>(a, blocks, lds, s);
     case kKindCliqueLgs | kKindClique:
       return launch_t<kKindCliqueLgs | kKindClique, CE>(a, blocks, lds, s);
     default: return launch_t<kKindAll, CE>(a, blocks, lds, s);

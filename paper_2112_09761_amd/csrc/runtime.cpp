@@ -72,6 +72,11 @@ struct Graph {
   int32_t* ren_lo_dst = nullptr;
   int64_t ren_n_lo = 0;
   bool ren_ready = false;
+  // 4-cycle wedge-aggregation roots on the relabelled graph: (v, part | parts << 16)
+  int32_t* wedge_src = nullptr;
+  int32_t* wedge_dst = nullptr;
+  int64_t n_wedge = 0;
+  int64_t wedge_key = -1;
   int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
   int32_t* lo_dst = nullptr;
   int64_t n_lo = 0;
@@ -99,6 +104,8 @@ struct Slot {
   void* d_meta = nullptr;  size_t d_meta_bytes = 0;    // jobs, plans, offsets
   unsigned long long* d_res = nullptr; size_t d_res_words = 0;  // results + queues + counters
   int32_t* d_fbuf = nullptr; size_t d_fbuf_bytes = 0;
+  unsigned int* d_zero = nullptr; size_t d_zero_bytes = 0;  // wedge counters
+  bool zero_dirty = true;
   void* h_stage = nullptr; size_t h_stage_bytes = 0;    // pinned
   unsigned long long* h_res = nullptr; size_t h_res_words = 0;  // pinned
   bool busy = false;
@@ -131,7 +138,7 @@ struct gpm_ctx {
   int64_t opt_lds_tile = 0, opt_max_batch = 4096, opt_serve_slots = kMaxSlots;
   int64_t opt_max_pending = 1 << 20;
   int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
-  int64_t opt_lgs_split = 1, opt_leaf_cap = 128;
+  int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
   gpm_stats stats{};
   Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
   // serving
@@ -180,6 +187,9 @@ static void free_view(GraphView& v) {
 static void free_graph(Graph& g) {
   free_view(g.sym);
   free_view(g.ren);
+  dev_free(g.wedge_src);
+  dev_free(g.wedge_dst);
+  g.wedge_src = g.wedge_dst = nullptr;
   dev_free(g.ren_lo_src);
   dev_free(g.ren_lo_dst);
   g.ren_lo_src = g.ren_lo_dst = nullptr;
@@ -422,6 +432,64 @@ static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
   return GPM_OK;
 }
 
+// Roots of the 4-cycle wedge aggregation on the relabelled graph, heaviest
+// first.  A root's work is at most sum over its lower neighbours u of d(u);
+// it gets ceil(work / share) disjoint endpoint ranges (share: a quarter of an
+// even split over `waves` waves).
+static gpm_status ensure_wedge(gpm_ctx* c, Graph& g, int64_t waves) {
+  gpm_status st = ensure_ren(c, g);
+  if (st) return st;
+  if (g.wedge_key == waves) return GPM_OK;
+  dev_free(g.wedge_src);
+  dev_free(g.wedge_dst);
+  g.wedge_src = g.wedge_dst = nullptr;
+  const HostCSR& R = g.ren_host;
+  std::vector<int32_t> roots;
+  std::vector<double> work;
+  double total = 0;
+  for (int64_t v = 0; v < R.n; ++v) {
+    int64_t e = std::lower_bound(R.col.begin() + R.rp[v], R.col.begin() + R.rp[v + 1], (int32_t)v) -
+                (R.col.begin() + R.rp[v]);
+    if (e < 2) continue;
+    double wk = 0;
+    for (int64_t p = R.rp[v]; p < R.rp[v] + e; ++p) {
+      int32_t u = R.col[p];
+      wk += (double)(R.rp[u + 1] - R.rp[u]);
+    }
+    roots.push_back((int32_t)v);
+    work.push_back(wk);
+    total += wk;
+  }
+  std::vector<int64_t> idx(roots.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int64_t)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+  const double share = std::max(total / (double)(waves * 4), 1.0);
+  std::vector<int32_t> src, dst;
+  for (int64_t i : idx) {
+    int64_t parts = std::min<int64_t>(1024, std::max<int64_t>(1, (int64_t)std::ceil(work[i] / share)));
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, roots[i]));
+    for (int64_t q = 0; q < parts; ++q) {
+      src.push_back(roots[i]);
+      dst.push_back((int32_t)(q | (parts << 16)));
+    }
+  }
+  g.n_wedge = (int64_t)src.size();
+  st = dev_upload(c, &g.wedge_src, src.data(), src.size());
+  if (st) return st;
+  st = dev_upload(c, &g.wedge_dst, dst.data(), dst.size());
+  if (st) return st;
+  g.bytes += src.size() * 8;
+  g.wedge_key = waves;
+  return GPM_OK;
+}
+
+static bool is_cycle4(const gpm_pattern& p) {
+  if (p.k != 4 || p.n_edges != 4) return false;
+  int deg[4] = {0, 0, 0, 0};
+  for (int i = 0; i < 8; ++i) deg[p.edges[i]]++;
+  return deg[0] == 2 && deg[1] == 2 && deg[2] == 2 && deg[3] == 2;
+}
+
 static Graph* find_graph(gpm_ctx* c, int32_t id) {
   auto it = c->graphs.find(id);
   return it == c->graphs.end() ? nullptr : it->second.get();
@@ -445,6 +513,8 @@ static int default_chunk(const gpm_ctx* c, int kind) {
     default: return 8;
   }
 }
+
+static int64_t kWedgeWaves(const gpm_ctx* c) { return (int64_t)c->cus * 8; }
 
 static int lds_tile(const gpm_ctx* c) {
   return c->opt_lds_tile > 0 ? (int)c->opt_lds_tile : 512;
@@ -545,6 +615,25 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     return GPM_OK;
   }
 
+  if (mode == GPM_EDGE_INDUCED && is_cycle4(p) && c->opt_cycle4_algo != 1) {
+    st = ensure_wedge(c, g, kWedgeWaves(c));
+    if (st) return st;
+    Job J{};
+    J.kind = kJobCycleWedge;
+    J.k = 4;
+    J.rp = g.ren.rp;
+    J.col = g.ren.col;
+    J.task_src = g.wedge_src;
+    J.task_dst = g.wedge_dst;
+    J.n_tasks = g.n_wedge;
+    J.vertex_tasks = 1;
+    J.chunk = 1;
+    J.cap = (int32_t)n;  // counter words per wave
+    js.jobs.push_back(J);
+    js.need_words.push_back(0);
+    qw.n_jobs += 1;
+    return GPM_OK;
+  }
   HostPlan hp;
   st = build_plan(p, mode, false, &hp, &err);
   if (st) return fail(c, st, err);
@@ -718,6 +807,7 @@ static void slot_free(Slot& s) {
   dev_free(s.d_meta);
   dev_free(s.d_res);
   dev_free(s.d_fbuf);
+  dev_free(s.d_zero);
   if (s.h_stage) (void)hipHostFree(s.h_stage);
   if (s.h_res) (void)hipHostFree(s.h_res);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
@@ -851,6 +941,18 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
                                        max_resident, &waves);
     if (s2) return fail(c, GPM_E_NOMEM, "frontier buffers do not fit the memory budget");
   }
+  // 4-cycle wedge jobs: one zero-initialised counter array per wave
+  int64_t zstride = 0;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].kind == kJobCycleWedge) zstride = std::max<int64_t>(zstride, jobs[i].cap);
+  zstride = (int64_t)align_up((size_t)zstride, 64);
+  if (zstride) {
+    waves = std::min<int64_t>(waves, kWedgeWaves(c));
+    const int64_t left = (int64_t)frontier_budget - waves * stride * 4;
+    const int64_t zw = left > 0 ? left / (zstride * 4) : 0;
+    if (zw < kWavesPerBlock) return fail(c, GPM_E_NOMEM, "wedge counters do not fit the memory budget");
+    waves = std::min(waves, zw);
+  }
   waves = std::max<int64_t>(kWavesPerBlock, waves / kWavesPerBlock * kWavesPerBlock);
   const int blocks = (int)(waves / kWavesPerBlock);
   const size_t fbytes = (size_t)waves * (size_t)stride * 4;
@@ -858,7 +960,20 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     st = grow_dev(c, (void**)&s.d_fbuf, &s.d_fbuf_bytes, fbytes);
     if (st) return st;
   }
-  *frontier_used = fbytes;
+  const size_t zbytes = (size_t)waves * (size_t)zstride * 4;
+  if (zbytes) {
+    void* before = s.d_zero;
+    st = grow_dev(c, (void**)&s.d_zero, &s.d_zero_bytes, zbytes);
+    if (st) return st;
+    if (before != (void*)s.d_zero) s.zero_dirty = true;
+    if (s.zero_dirty) {
+      if (launch_fill_u64((unsigned long long*)s.d_zero, (int64_t)(s.d_zero_bytes / 8), 0ull,
+                          s.stream))
+        return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+    }
+    s.zero_dirty = true;  // until this group completes (every task restores zeros)
+  }
+  *frontier_used = fbytes + zbytes;
 
   const size_t lds_bytes = (size_t)lds_words * 4 * kWavesPerBlock;
 
@@ -937,6 +1052,8 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs)) != 0;
     a.lds_words = uses_lds ? lds_words : 0;
     a.lgs_tile = lgs_T;
+    a.zbuf = (L.kinds & kKindCycleWedge) ? s.d_zero : nullptr;
+    a.zstride = zstride;
     size_t lb = uses_lds ? lds_bytes : 0;
     int e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
     if (e) return fail(c, GPM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
@@ -959,6 +1076,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
 
 static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
   HIP_TRY(c, hipStreamSynchronize(s.stream));
+  s.zero_dirty = false;
   float ms = 0.f;
   if (s.n_launch > 0) HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
   c->stats.kernel_ms = ms;
@@ -1067,6 +1185,7 @@ static gpm_status progress(gpm_ctx* c) {
     }
     s.queries.clear();
     s.busy = false;
+    s.zero_dirty = false;
     c->serve_frontier_in_use -= s.frontier_bytes_in_use;
     s.frontier_bytes_in_use = 0;
   }
@@ -1192,6 +1311,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "count_elements") c->opt_count_elements = v != 0;
   else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
+  else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }

@@ -157,21 +157,23 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
     gid = ctx.load(g)
     exp = {n: oracle.count(g, n, True) for n in ["clique4", "clique5", "cycle4", "diamond",
                                                  "tailed_triangle", "path4"]}
+    exp_c4e = oracle.cycle4(g)
     try:
         for opt, vals in [("chunk", [1, 3, 64]), ("waves_per_cu", [1, 4, 32]),
                           ("lds_tile", [32, 64, 4096]), ("clique_lds", [0]),
                           ("granularity", [1]), ("clique_algo", [1, 2]),
                           ("lgs_tile", [64, 128]), ("lgs_max", [64, 100]),
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
-                          ("rename", [0])]:
+                          ("rename", [0]), ("cycle4_algo", [1, 2])]:
             for v in vals:
                 ctx.set_option(opt, v)
                 for n, e in exp.items():
                     assert ctx.count(gid, n, V) == e, (opt, v, n)
+                assert ctx.count(gid, "cycle4", E) == exp_c4e, (opt, v)
             ctx.set_option(opt, {"chunk": 0, "waves_per_cu": 0, "lds_tile": 0,
                                  "clique_lds": 1, "granularity": 0, "clique_algo": 0,
                                  "lgs_tile": 256, "lgs_max": 1024, "lgs_split": 1,
-                                 "leaf_cap": 128, "rename": 1}[opt])
+                                 "leaf_cap": 128, "rename": 1, "cycle4_algo": 0}[opt])
     finally:
         ctx.unload(gid)
 

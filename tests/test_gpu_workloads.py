@@ -65,7 +65,7 @@ def test_chung_lu_4m(ctx):
         n4 = gold["counts"]["nonind4"]  # path4, star3, cycle4, tailed_triangle, diamond, clique4
         print("chung_lu motifs3", flush=True)
         assert ctx.motifs(gid, 3) == m3
-        for name, idx in (("diamond", 4), ("tailed_triangle", 3)):
+        for name, idx in (("diamond", 4), ("tailed_triangle", 3), ("cycle4", 2)):
             print("chung_lu", name, flush=True)
             assert ctx.count(gid, name, 1) == n4[idx], name
     finally:
