@@ -142,8 +142,13 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     at most this long are counted one per lane (0 = off)
  *   "count_elements"  1 = instrumented kernels count intersected elements
  *                     (slower; never used for timing)
- *   "autotune"        1 = time candidate configurations on first use of a
- *                     (graph, pattern) pair and cache the winner
+ *   "autotune"        1 = on the first gpm_count of a (graph, pattern, mode)
+ *                     that takes at least "tune_min_ms" (default 20), try the
+ *                     knob values of its search space (LDS tile, waves per
+ *                     CU, chunk, leaf mode, granularity, renaming) by
+ *                     coordinate descent -- every trial must return the same
+ *                     count, else GPM_E_DEVICE -- and reuse the fastest
+ *                     values on later calls of that triple
  * Unknown keys give GPM_E_INVAL. */
 gpm_status gpm_set_option(gpm_ctx *ctx, const char *key, int64_t value);
 

@@ -375,60 +375,38 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
     }
     return c;
   }
-  // k = 5: for every local edge (i, j) and every l in M = R_i & R_j add
-  // |M & R_l|.  Each lane walks the bits of its own M; a lane whose M is
-  // exhausted takes the next local edge at once (ballot + mbcnt hand-out),
-  // so the wave stays busy although the |M| differ.
-  uint64_t M[kLgsMaxWords];
-  int32_t next = p0;
-  bool have = false;
-  int32_t x = 0;         // current word of M
-  uint64_t m = 0;        // remaining bits of M[x]
-  for (;;) {
-    const bool need = !have;
-    const uint64_t nm = wave_ballot(need);
-    const int32_t t = next + (int32_t)lanes_below(nm);
-    next = min(next + (int32_t)__popcll(nm), p1);   // never runs past the range
-    if (need && t < p1) {
-      int32_t i = upper_bound(P + 1, d, t);
-      int32_t r = t - P[i];
-      const TR* Ri = R + (size_t)i * W;
-      int32_t w = 0;
-      for (;; ++w) {
-        int32_t pc = __popcll(Ri[w]);
-        if (r < pc) break;
-        r -= pc;
+  // k = 5: for every local edge (i, j) (one per lane) and every l in
+  // M = R_i & R_j add |M & R_l|; M stays in registers.
+  for (int32_t tb = p0; tb < p1; tb += 64) {
+    const int32_t t = tb + l;
+    if (t >= p1) continue;
+    int32_t i = upper_bound(P + 1, d, t);
+    int32_t r = t - P[i];
+    const TR* Ri = R + (size_t)i * W;
+    int32_t w = 0;
+    for (;; ++w) {
+      int32_t pc = __popcll(Ri[w]);
+      if (r < pc) break;
+      r -= pc;
+    }
+    const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
+    uint64_t M[kLgsMaxWords];
+#pragma unroll
+    for (int x = 0; x < kLgsMaxWords; ++x) M[x] = (x < W) ? (Ri[x] & Rj[x]) : 0ull;
+    if (CE) ec.words += (uint64_t)W;
+#pragma unroll
+    for (int x = 0; x < kLgsMaxWords; ++x) {
+      if (x >= W) break;
+      uint64_t m = M[x];
+      while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1ull;
+        const TR* Rl = R + (size_t)(x * 64 + b) * W;
+#pragma unroll
+        for (int y = 0; y < kLgsMaxWords; ++y)
+          if (y < W && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+        if (CE) ec.words += (uint64_t)W;
       }
-      const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
-#pragma unroll
-      for (int y = 0; y < kLgsMaxWords; ++y) M[y] = (y < W) ? (Ri[y] & Rj[y]) : 0ull;
-      if (CE) ec.words += (uint64_t)W;
-      x = 0;
-      m = M[0];
-      have = true;
-    }
-    if (have && m == 0) {
-      // advance to the next non-empty word of M (static register indices)
-      while (m == 0 && ++x < W) {
-        uint64_t v = 0;
-#pragma unroll
-        for (int y = 1; y < kLgsMaxWords; ++y) v = (x == y) ? M[y] : v;
-        m = v;
-      }
-      if (m == 0) have = false;
-    }
-    if (wave_ballot(have) == 0ull) {
-      if (next >= p1) break;
-      continue;
-    }
-    if (have) {
-      int b = __builtin_ctzll(m);
-      m &= m - 1ull;
-      const TR* Rl = R + (size_t)(x * 64 + b) * W;
-#pragma unroll
-      for (int y = 0; y < kLgsMaxWords; ++y)
-        if (y < W) c += (uint64_t)__popcll(M[y] & Rl[y]);
-      if (CE) ec.words += (uint64_t)W;
     }
   }
   return c;

@@ -139,6 +139,10 @@ struct gpm_ctx {
   int64_t opt_max_pending = 1 << 20;
   int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
+  int64_t opt_tune_min_ms = 20;
+  // autotuner cache: (graph, pattern, mode) -> tuned knob values
+  std::map<std::string, std::vector<std::pair<std::string, int64_t>>> tuned;
+  bool tuning = false;
   gpm_stats stats{};
   Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
   // serving
@@ -691,6 +695,40 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
 }
 
 static void named(const char* name, gpm_pattern* p);
+
+// ---------------------------------------------------------------------------
+// autotuner: task granularity, chunk size, LDS tile, waves per CU, leaf mode
+// ---------------------------------------------------------------------------
+
+static int64_t* knob(gpm_ctx* c, const std::string& k) {
+  if (k == "granularity") return &c->opt_granularity;
+  if (k == "chunk") return &c->opt_chunk;
+  if (k == "waves_per_cu") return &c->opt_waves_per_cu;
+  if (k == "lgs_tile") return &c->opt_lgs_tile;
+  if (k == "leaf_cap") return &c->opt_leaf_cap;
+  if (k == "rename") return &c->opt_rename;
+  if (k == "lds_tile") return &c->opt_lds_tile;
+  return nullptr;
+}
+
+// Search space per kind of query: coordinate descent over these knobs, in
+// this order, each value tried once with the others held at their best.
+static std::vector<std::pair<std::string, std::vector<int64_t>>> tune_space(const gpm_pattern& p,
+                                                                             int mode) {
+  const bool clique = p.n_edges == p.k * (p.k - 1) / 2;
+  if (clique && p.k <= 5)
+    return {{"lgs_tile", {256, 192, 128}}, {"waves_per_cu", {16, 12, 24}}, {"chunk", {0, 2}}};
+  if (clique) return {{"lds_tile", {0, 256, 128}}, {"chunk", {0, 4, 16}}, {"waves_per_cu", {16, 12}}};
+  (void)mode;
+  return {{"leaf_cap", {128, 0, 32, 512}}, {"chunk", {0, 2, 32}}, {"granularity", {0, 1}},
+          {"rename", {1, 0}}, {"waves_per_cu", {16, 12}}};
+}
+
+static std::string tune_key(int32_t gid, const gpm_pattern& p, int mode) {
+  std::string k = std::to_string(gid) + ":" + std::to_string(mode) + ":" + std::to_string(p.k);
+  for (int i = 0; i < 2 * p.n_edges; ++i) k += "," + std::to_string(p.edges[i]);
+  return k;
+}
 
 // k-motif counting (Sec. 2.1): fused triangle-rooted edge job, degree job,
 // 4-clique on the DAG and the 4-cycle plan (kernel fission, Sec. 5.3).
@@ -1316,6 +1354,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;
+  else if (k == "tune_min_ms") { if (v < 0) return fail(c, GPM_E_INVAL, "tune_min_ms >= 0"); c->opt_tune_min_ms = v; }
   else if (k == "max_batch") { if (v < 1) return fail(c, GPM_E_INVAL, "max_batch >= 1"); c->opt_max_batch = v; }
   else if (k == "serve_slots") { if (v < 1 || v > kMaxSlots) return fail(c, GPM_E_INVAL, "serve_slots 1..4"); c->opt_serve_slots = v; }
   else if (k == "max_pending") { if (v < 1) return fail(c, GPM_E_INVAL, "max_pending >= 1"); c->opt_max_pending = v; }
@@ -1498,6 +1537,18 @@ gpm_status gpm_frontier_waves(int64_t free_bytes, int32_t x_levels, int64_t cap_
   return GPM_OK;
 }
 
+static gpm_status count_once(gpm_ctx* c, const gpm_query& q, uint64_t* out0) {
+  JobPlanSet js;
+  std::vector<QueryWork> qs(1);
+  gpm_status st = build_query(c, q, js, qs[0]);
+  if (st) return st;
+  uint64_t out[6];
+  st = run_sync(c, js, qs, true, out);
+  if (st) return st;
+  *out0 = out[0];
+  return GPM_OK;
+}
+
 gpm_status gpm_count(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, int mode,
                      uint64_t* count_out) {
   if (!c || !pattern || !count_out) return GPM_E_INVAL;
@@ -1507,14 +1558,58 @@ gpm_status gpm_count(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, i
   q.mode_or_k = mode;
   q.pattern = *pattern;
   HIP_TRY(c, hipSetDevice(c->device));
-  JobPlanSet js;
-  std::vector<QueryWork> qs(1);
-  gpm_status st = build_query(c, q, js, qs[0]);
-  if (st) return st;
-  uint64_t out[6];
-  st = run_sync(c, js, qs, true, out);
-  if (st) return st;
-  *count_out = out[0];
+  if (!c->opt_autotune || c->tuning) return count_once(c, q, count_out);
+
+  const std::string key = tune_key(graph_id, *pattern, mode);
+  auto space = tune_space(*pattern, mode);
+  // remember the caller's knob values; tuned values apply to this call only
+  std::vector<std::pair<int64_t*, int64_t>> saved;
+  for (auto& kv : space) saved.push_back({knob(c, kv.first), *knob(c, kv.first)});
+  auto restore = [&]() {
+    for (auto& sv : saved) *sv.first = sv.second;
+  };
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    for (auto& kv : it->second) *knob(c, kv.first) = kv.second;
+    gpm_status st = count_once(c, q, count_out);
+    restore();
+    c->stats.variant = 1;
+    return st;
+  }
+  uint64_t ref = 0;
+  gpm_status st = count_once(c, q, &ref);
+  if (st) { restore(); return st; }
+  double best = c->stats.kernel_ms;
+  std::vector<std::pair<std::string, int64_t>> cfg;
+  for (auto& kv : space) cfg.push_back({kv.first, *knob(c, kv.first)});
+  if (best >= (double)c->opt_tune_min_ms) {
+    c->tuning = true;
+    for (size_t d = 0; d < space.size(); ++d) {
+      for (int64_t v : space[d].second) {
+        if (v == cfg[d].second) continue;
+        for (auto& kv : cfg) *knob(c, kv.first) = kv.second;
+        *knob(c, space[d].first) = v;
+        uint64_t got = 0;
+        st = count_once(c, q, &got);
+        if (st) break;
+        if (got != ref) {
+          c->tuning = false;
+          restore();
+          return fail(c, GPM_E_DEVICE, "autotuner: configurations disagree on the count");
+        }
+        if (c->stats.kernel_ms < best) {
+          best = c->stats.kernel_ms;
+          cfg[d].second = v;
+        }
+      }
+      if (st) break;
+    }
+    c->tuning = false;
+    if (st) { restore(); return st; }
+  }
+  c->tuned[key] = cfg;
+  restore();
+  *count_out = ref;
   return GPM_OK;
 }
 

@@ -178,6 +178,23 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
         ctx.unload(gid)
 
 
+def test_autotuner_keeps_counts(ctx, oracle):
+    g = synth.rmat(12, 12, seed=901)
+    gid = ctx.load(g)
+    try:
+        ctx.set_option("autotune", 1)
+        ctx.set_option("tune_min_ms", 0)
+        for name, mode in [("clique4", V), ("clique5", V), ("diamond", E), ("path4", V)]:
+            exp = oracle.count(g, name, mode == V)
+            assert ctx.count(gid, name, mode) == exp, name    # tunes
+            assert ctx.count(gid, name, mode) == exp, name    # cached configuration
+            assert ctx.stats()["variant"] == 1
+    finally:
+        ctx.set_option("autotune", 0)
+        ctx.set_option("tune_min_ms", 20)
+        ctx.unload(gid)
+
+
 def test_large_roots_take_edge_kernel(ctx, oracle):
     """Roots above the local-graph limit go to the edge-parallel kernel; the
     split must not change any count (K_n has out-degrees up to n - 1)."""
