@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--option", action="append", default=[],
                     help="library option key=value (tuning sweeps)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (x steps), the "
+                         "reference for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -316,6 +319,15 @@ def main():
     import torch
     from paper_2112_09761_amd import gpm
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": args.steps}), flush=True)
+        return
     ctx = gpm.Context(0, torch.cuda.current_stream())
     for kv in args.option:
         k, v = kv.split("=")
