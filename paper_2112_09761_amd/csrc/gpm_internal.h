@@ -80,7 +80,9 @@ struct Job {
   int32_t cap;             // frontier capacity in elements (max set size)
   int32_t lds_ok;          // clique job: sets fit the LDS tile
   int32_t leaf_cap;        // DFS job: lane-per-candidate leaves up to this size
-  int32_t pad;
+  int32_t ordered;         // clique job: out-lists follow the orientation order
+                           // (u -> v iff u < v), so local bitmap rows are
+                           // upper triangular
 };
 
 struct KernelArgs {

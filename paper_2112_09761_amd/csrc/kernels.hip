@@ -293,8 +293,8 @@ template <bool CE, typename TL, typename TP, typename TR>
 __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
                                                int32_t u, int32_t d, int32_t part,
-                                               int32_t parts, TL* L, TP* P, TR* R,
-                                               ElemCounter& ec) {
+                                               int32_t parts, bool ordered, TL* L, TP* P,
+                                               TR* R, ElemCounter& ec) {
   const int l = lane_id();
   const int32_t W = (d + 63) >> 6;
   const int32_t* Nu = col + rp[u];
@@ -369,9 +369,12 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
         if (r < pc) break;
         r -= pc;
       }
-      const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
-      for (int32_t x = 0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
-      if (CE) ec.words += (uint64_t)W;
+      const int32_t j = w * 64 + select64(Ri[w], r);
+      const TR* Rj = R + (size_t)j * W;
+      // ordered: R_j has bits only above j
+      const int32_t x0 = ordered ? ((j + 1) >> 6) : 0;
+      for (int32_t x = x0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
+      if (CE) ec.words += (uint64_t)(W - x0);
     }
     return c;
   }
@@ -389,11 +392,14 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       if (r < pc) break;
       r -= pc;
     }
-    const TR* Rj = R + (size_t)(w * 64 + select64(Ri[w], r)) * W;
+    const int32_t j = w * 64 + select64(Ri[w], r);
+    const TR* Rj = R + (size_t)j * W;
+    // ordered: R_j (and so M) has bits only above j, R_l only above l
+    const int jw = ordered ? ((j + 1) >> 6) : 0;
     uint64_t M[kLgsMaxWords];
 #pragma unroll
-    for (int x = 0; x < kLgsMaxWords; ++x) M[x] = (x < W) ? (Ri[x] & Rj[x]) : 0ull;
-    if (CE) ec.words += (uint64_t)W;
+    for (int x = 0; x < kLgsMaxWords; ++x) M[x] = (x < W && x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
+    if (CE) ec.words += (uint64_t)(W - jw);
 #pragma unroll
     for (int x = 0; x < kLgsMaxWords; ++x) {
       if (x >= W) break;
@@ -401,11 +407,13 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       while (m) {
         const int b = __builtin_ctzll(m);
         m &= m - 1ull;
-        const TR* Rl = R + (size_t)(x * 64 + b) * W;
+        const int lidx = x * 64 + b;
+        const int lw = ordered ? ((lidx + 1) >> 6) : 0;
+        const TR* Rl = R + (size_t)lidx * W;
 #pragma unroll
         for (int y = 0; y < kLgsMaxWords; ++y)
-          if (y < W && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
-        if (CE) ec.words += (uint64_t)W;
+          if (y < W && y >= lw && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+        if (CE) ec.words += (uint64_t)(W - lw);
       }
     }
   }
@@ -877,12 +885,14 @@ gpm_persistent(KernelArgs a) {
           int32_t* L = my;
           int32_t* Pp = L + a.lgs_tile;
           unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, L, Pp, R, ec);
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, R,
+                                   ec);
         } else {
           int32_t* L = fb;
           int32_t* Pp = fb + J.cap;
           unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, L, Pp, R, ec);
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, R,
+                                   ec);
         }
       }
     } else if ((KINDS & kKindCycleWedge) && kind == kJobCycleWedge) {

@@ -52,6 +52,7 @@ struct Graph {
   GraphView dag;            // degree-oriented DAG (lazy) or the given DAG
   HostCSR dag_host;
   bool dag_ready = false;
+  bool dag_ordered = false;   // out-lists ordered as the orientation (ids = ranks)
   // local-graph clique tasks: vertices by out-degree, descending (lazy)
   int32_t* lgs_vtx = nullptr;
   std::vector<int64_t> lgs_deg;     // out-degree of lgs order position i
@@ -239,34 +240,36 @@ static gpm_status upload_view(gpm_ctx* c, const HostCSR& h, bool with_src, Graph
   return GPM_OK;
 }
 
+static gpm_status ensure_ren(gpm_ctx* c, Graph& g);
+
 // Orientation by (degree, id) (Sec. 3 "Graph Loader and Preprocessor":
 // orientation halves the edges and shrinks the maximum degree).
-static HostCSR orient_by_degree(const HostCSR& g) {
-  HostCSR d;
-  d.n = g.n;
-  d.rp.assign(g.n + 1, 0);
-  auto before = [&](int64_t u, int64_t v) {
-    int64_t du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];
-    return du < dv || (du == dv && u < v);
-  };
-  for (int64_t u = 0; u < g.n; ++u) {
-    int64_t c = 0;
-    for (int64_t p = g.rp[u]; p < g.rp[u + 1]; ++p) c += before(u, g.col[p]);
-    d.rp[u + 1] = d.rp[u] + c;
-  }
-  d.col.resize(d.rp[g.n]);
-  for (int64_t u = 0; u < g.n; ++u) {
-    int64_t o = d.rp[u];
-    for (int64_t p = g.rp[u]; p < g.rp[u + 1]; ++p)
-      if (before(u, g.col[p])) d.col[o++] = g.col[p];
-  }
-  return d;
-}
-
 static gpm_status ensure_dag(gpm_ctx* c, Graph& g) {
   if (g.dag_ready) return GPM_OK;
-  if (g.dag_only) g.dag_host = g.host;
-  else g.dag_host = orient_by_degree(g.host);
+  if (g.dag_only) {
+    g.dag_host = g.host;
+  } else {
+    // orient the graph relabelled by ascending (degree, id): u -> v iff u < v,
+    // so every out-list is in the DAG's topological order
+    gpm_status st = ensure_ren(c, g);
+    if (st) return st;
+    const HostCSR& R = g.ren_host;
+    HostCSR& D = g.dag_host;
+    D.n = R.n;
+    D.rp.assign(R.n + 1, 0);
+    for (int64_t u = 0; u < R.n; ++u) {
+      int64_t lo = std::upper_bound(R.col.begin() + R.rp[u], R.col.begin() + R.rp[u + 1], (int32_t)u) -
+                   R.col.begin();
+      D.rp[u + 1] = D.rp[u] + (R.rp[u + 1] - lo);
+    }
+    D.col.resize(D.rp[R.n]);
+    for (int64_t u = 0; u < R.n; ++u) {
+      int64_t lo = std::upper_bound(R.col.begin() + R.rp[u], R.col.begin() + R.rp[u + 1], (int32_t)u) -
+                   R.col.begin();
+      std::copy(R.col.begin() + lo, R.col.begin() + R.rp[u + 1], D.col.begin() + D.rp[u]);
+    }
+    g.dag_ordered = true;
+  }
   gpm_status st = upload_view(c, g.dag_host, true, &g.dag, &g.bytes);
   if (st) return st;
   g.dag_ready = true;
@@ -553,6 +556,7 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     J.n_tasks = g.dag.nnz;
     J.k = p.k;
     J.cap = (int32_t)cap;
+    J.ordered = g.dag_ordered ? 1 : 0;
     const bool lgs = c->opt_clique_lds && c->opt_clique_algo != 1 && p.k <= 5;
     if (lgs) {
       // local graph search with bitmaps for roots with at most
