@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--workload", default="clique",
                     choices=["clique", "triangle", "batch", "serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default kernel knobs (fixed dispatch sequence)")
     ap.add_argument("--option", action="append", default=[],
                     help="library option key=value (tuning sweeps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -91,7 +93,8 @@ def run_clique(args, ctx, torch):
         inst_lgs[k] = ctx.stats()
     ctx.set_option("count_elements", 0)
     pats = {k: (k, [(i, j) for i in range(k) for j in range(i + 1, k)]) for k in (4, 5)}
-    ctx.set_option("autotune", 1)   # the first (warm-up) call of each count tunes
+    if not args.no_autotune:
+        ctx.set_option("autotune", 1)   # the first (warm-up) call of each count tunes
     for _ in range(max(args.warmup, 1)):
         for k in (4, 5):
             ctx.count(gid, pats[k])

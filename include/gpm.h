@@ -173,6 +173,13 @@ gpm_status gpm_load_csr(gpm_ctx *ctx, int64_t n, int64_t nnz,
                         const int64_t *row_ptr, const int32_t *col,
                         uint32_t flags, int32_t *graph_id_out);
 
+/* The checks of gpm_load_csr on host arrays, without a context or device:
+ * GPM_OK, GPM_E_INVAL (bad sizes / null / conflicting or device flags) or
+ * GPM_E_CSR (not canonical; with GPM_VALIDATE also asymmetric, or a DAG with
+ * both directions of an edge or a cycle). */
+gpm_status gpm_validate_csr(int64_t n, int64_t nnz, const int64_t *row_ptr,
+                            const int32_t *col, uint32_t flags);
+
 gpm_status gpm_unload(gpm_ctx *ctx, int32_t graph_id);
 
 gpm_status gpm_graph_info(gpm_ctx *ctx, int32_t graph_id, gpm_graph_meta *out);

@@ -1299,7 +1299,75 @@ static gpm_status progress(gpm_ctx* c) {
 // C ABI
 // ---------------------------------------------------------------------------
 
+// Canonical-form checks of a CSR (Table 3's note: symmetric, no loops, no
+// duplicates; sorted lists, Sec. 3), plus symmetry / acyclicity with
+// GPM_VALIDATE.
+static gpm_status validate_csr(const HostCSR& h, uint32_t flags, std::string* why) {
+  const int64_t n = h.n;
+  const int64_t nnz = (int64_t)h.col.size();
+  const bool dag = (flags & GPM_CSR_DAG) != 0;
+  const bool sym = !dag;
+  auto bad = [&](const char* m) {
+    *why = m;
+    return GPM_E_CSR;
+  };
+  if (h.rp[0] != 0 || h.rp[n] != nnz) return bad("row_ptr[0] != 0 or row_ptr[n] != nnz");
+  for (int64_t u = 0; u < n; ++u) {
+    if (h.rp[u + 1] < h.rp[u]) return bad("row_ptr not monotone");
+    for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) {
+      int32_t v = h.col[p];
+      if (v < 0 || v >= n) return bad("neighbour id out of range");
+      if (v == u) return bad("self loop");
+      if (p > h.rp[u] && h.col[p - 1] >= v) return bad("neighbour list unsorted or duplicated");
+    }
+  }
+  auto has = [&](int64_t u, int32_t v) {
+    return std::binary_search(h.col.begin() + h.rp[u], h.col.begin() + h.rp[u + 1], v);
+  };
+  if (flags & GPM_VALIDATE) {
+    for (int64_t u = 0; u < n; ++u)
+      for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) {
+        bool back = has(h.col[p], (int32_t)u);
+        if (sym && !back) return bad("graph not symmetric");
+        if (dag && back) return bad("DAG holds both directions of an edge");
+      }
+    if (dag) {  // acyclic (Kahn)
+      std::vector<int64_t> indeg(n, 0);
+      for (int64_t p = 0; p < nnz; ++p) indeg[h.col[p]]++;
+      std::vector<int64_t> q;
+      for (int64_t u = 0; u < n; ++u)
+        if (!indeg[u]) q.push_back(u);
+      int64_t seen = 0;
+      while (!q.empty()) {
+        int64_t u = q.back();
+        q.pop_back();
+        ++seen;
+        for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p)
+          if (--indeg[h.col[p]] == 0) q.push_back(h.col[p]);
+      }
+      if (seen != n) return bad("oriented graph has a cycle");
+    }
+  } else if (sym && (nnz & 1)) {
+    return bad("symmetric graph with an odd number of entries");
+  }
+  return GPM_OK;
+}
+
 extern "C" {
+
+gpm_status gpm_validate_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                            uint32_t flags) {
+  if (n < 0 || nnz < 0 || n >= (int64_t)INT32_MAX || !row_ptr || (nnz > 0 && !col))
+    return GPM_E_INVAL;
+  if ((flags & GPM_CSR_DAG) && (flags & GPM_CSR_SYMMETRIC)) return GPM_E_INVAL;
+  if (flags & GPM_PTRS_DEVICE) return GPM_E_INVAL;
+  HostCSR h;
+  h.n = n;
+  h.rp.assign(row_ptr, row_ptr + n + 1);
+  if (nnz) h.col.assign(col, col + nnz);
+  std::string why;
+  return validate_csr(h, flags, &why);
+}
 
 gpm_status gpm_create(gpm_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes) {
   if (!out) return GPM_E_INVAL;
@@ -1395,44 +1463,10 @@ gpm_status gpm_load_csr(gpm_ctx* c, int64_t n, int64_t nnz, const int64_t* row_p
     std::memcpy(h.rp.data(), row_ptr, (n + 1) * 8);
     if (nnz) std::memcpy(h.col.data(), col, nnz * 4);
   }
-  // canonical form (Table 3's note: no loops, no duplicates; sorted lists, Sec. 3)
-  if (h.rp[0] != 0 || h.rp[n] != nnz) return fail(c, GPM_E_CSR, "row_ptr[0] != 0 or row_ptr[n] != nnz");
-  for (int64_t u = 0; u < n; ++u) {
-    if (h.rp[u + 1] < h.rp[u]) return fail(c, GPM_E_CSR, "row_ptr not monotone");
-    for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) {
-      int32_t v = h.col[p];
-      if (v < 0 || v >= n) return fail(c, GPM_E_CSR, "neighbour id out of range");
-      if (v == u) return fail(c, GPM_E_CSR, "self loop");
-      if (p > h.rp[u] && h.col[p - 1] >= v) return fail(c, GPM_E_CSR, "neighbour list unsorted or duplicated");
-    }
-  }
-  auto has = [&](int64_t u, int32_t v) {
-    return std::binary_search(h.col.begin() + h.rp[u], h.col.begin() + h.rp[u + 1], v);
-  };
-  if (flags & GPM_VALIDATE) {
-    for (int64_t u = 0; u < n; ++u)
-      for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p) {
-        bool back = has(h.col[p], (int32_t)u);
-        if (sym && !back) return fail(c, GPM_E_CSR, "graph not symmetric");
-        if (dag && back) return fail(c, GPM_E_CSR, "DAG holds both directions of an edge");
-      }
-    if (dag) {  // acyclic (Kahn)
-      std::vector<int64_t> indeg(n, 0);
-      for (int64_t p = 0; p < nnz; ++p) indeg[h.col[p]]++;
-      std::vector<int64_t> q;
-      for (int64_t u = 0; u < n; ++u) if (!indeg[u]) q.push_back(u);
-      int64_t seen = 0;
-      while (!q.empty()) {
-        int64_t u = q.back();
-        q.pop_back();
-        ++seen;
-        for (int64_t p = h.rp[u]; p < h.rp[u + 1]; ++p)
-          if (--indeg[h.col[p]] == 0) q.push_back(h.col[p]);
-      }
-      if (seen != n) return fail(c, GPM_E_CSR, "oriented graph has a cycle");
-    }
-  } else if (sym && (nnz & 1)) {
-    return fail(c, GPM_E_CSR, "symmetric graph with an odd number of entries");
+  {
+    std::string why;
+    gpm_status vs = validate_csr(h, flags, &why);
+    if (vs) return fail(c, vs, why);
   }
   g->m = dag ? nnz : nnz / 2;
   if (!dag) {

@@ -40,7 +40,7 @@ EXPORTS = [
     "gpm_load_csr", "gpm_unload", "gpm_graph_info", "gpm_pattern_clique",
     "gpm_pattern_named", "gpm_pattern_from_edges", "gpm_plan", "gpm_frontier_waves",
     "gpm_count", "gpm_motifs", "gpm_count_batch", "gpm_submit", "gpm_poll", "gpm_wait",
-    "gpm_inflight",
+    "gpm_inflight", "gpm_validate_csr",
 ]
 
 
@@ -123,6 +123,7 @@ def lib():
         L.gpm_poll.argtypes = [c_vp, c_i64, P(ctypes.c_int), P(c_u64)]
         L.gpm_wait.argtypes = [c_vp, c_i64, c_i64, P(c_u64)]
         L.gpm_inflight.argtypes = [c_vp, P(c_i64)]
+        L.gpm_validate_csr.argtypes = [c_i64, c_i64, c_vp, c_vp, ctypes.c_uint32]
         for name in EXPORTS:
             if name != "gpm_last_error":
                 getattr(L, name).restype = ctypes.c_int32
@@ -188,6 +189,17 @@ def frontier_waves(free_bytes, x_levels, cap_elems, n_tasks, max_resident) -> in
     _check(lib().gpm_frontier_waves(free_bytes, x_levels, cap_elems, n_tasks, max_resident,
                                     ctypes.byref(out)))
     return out.value
+
+
+def validate_csr(row_ptr, col, flags: int = GPM_CSR_SYMMETRIC) -> int:
+    """gpm_validate_csr on host arrays; returns the status code."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    nnz = cl.size
+    if nnz == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    return lib().gpm_validate_csr(rp.size - 1, nnz, rp.ctypes.data_as(c_vp),
+                                  cl.ctypes.data_as(c_vp), flags)
 
 
 def count_query(graph_id, pattern, mode) -> Query:

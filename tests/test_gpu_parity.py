@@ -273,3 +273,57 @@ def test_serving_alone_vs_mix(ctx, oracle):
     finally:
         for gid in ids:
             ctx.unload(gid)
+
+
+def test_error_paths_on_device(ctx):
+    """Load-time validation, unknown ids, bad modes, unsupported patterns on a
+    DAG-only graph, a memory budget too small for any frontier, and a full
+    serving queue all return their status codes (no abort, no count)."""
+    import numpy as np
+    from paper_2112_09761_amd import gpm
+    with pytest.raises(gpm.GpmError) as e:
+        ctx.load_csr(np.array([0, 1, 2]), np.array([0, 1]))          # self loops
+    assert e.value.status == -2
+    g = synth.rmat(9, 8, seed=951)
+    gid = ctx.load(g)
+    with pytest.raises(gpm.GpmError) as e:
+        ctx.count(gid, "triangle", 7)
+    assert e.value.status == -1
+    with pytest.raises(gpm.GpmError) as e:
+        ctx.count(gid, (4, [(0, 1), (2, 3)]))                        # disconnected
+    assert e.value.status == -3
+    # a DAG-only graph supports cliques only
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    keep = g.col > src
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src[keep], minlength=g.n), out=rp[1:])
+    did = ctx.load_csr(rp, g.col[keep], gpm.GPM_CSR_DAG | gpm.GPM_VALIDATE)
+    assert ctx.count(did, "clique4") == ctx.count(gid, "clique4")
+    with pytest.raises(gpm.GpmError) as e:
+        ctx.count(did, "diamond", 1)
+    assert e.value.status == -6
+    ctx.unload(did)
+    # budget too small for even one wave's frontier
+    ctx.set_option("budget", 1024)
+    try:
+        with pytest.raises(gpm.GpmError) as e:
+            ctx.count(gid, "diamond", 1)
+        assert e.value.status == -4
+    finally:
+        ctx.set_option("budget", 1 << 36)
+    # serving: a full pending list says busy, the queued query still completes
+    ctx.set_option("max_pending", 1)
+    try:
+        t1 = ctx.submit(gpm.count_query(gid, "clique5", 0))
+        extra = []
+        for _ in range(64):
+            try:
+                extra.append(ctx.submit(gpm.count_query(gid, "clique4", 0)))
+            except gpm.GpmError as err:
+                assert err.status == -7
+        assert ctx.wait(t1)[0] == ctx.count(gid, "clique5")
+        for t in extra:
+            ctx.wait(t)
+    finally:
+        ctx.set_option("max_pending", 1 << 20)
+    ctx.unload(gid)

@@ -110,3 +110,35 @@ def test_frontier_sizing():
     assert gpm.frontier_waves(10**9, 0, 1000, 10**9, 4096) == 4096
     with pytest.raises(gpm.GpmError):
         gpm.frontier_waves(100, 1, 1000, 10, 10)
+
+
+def test_validate_csr_error_paths():
+    """gpm_load_csr's input checks (host only): canonical CSR accepted, every
+    kind of malformed input rejected with GPM_E_CSR or GPM_E_INVAL."""
+    import numpy as np
+    from paper_2112_09761_amd import synth
+    OK, INVAL, CSR = 0, -1, -2
+    g = synth.erdos_renyi(50, 0.2, 3)
+    assert gpm.validate_csr(g.row_ptr, g.col) == OK
+    assert gpm.validate_csr(g.row_ptr, g.col, gpm.GPM_CSR_SYMMETRIC | gpm.GPM_VALIDATE) == OK
+    e = synth.empty(7)
+    assert gpm.validate_csr(e.row_ptr, e.col) == OK
+
+    def bad(rp, col, flags=gpm.GPM_CSR_SYMMETRIC, exp=CSR):
+        assert gpm.validate_csr(np.array(rp), np.array(col), flags) == exp
+
+    bad([0, 2, 3, 4], [2, 1, 0, 0])                 # unsorted list
+    bad([0, 2, 3, 4], [1, 1, 0, 0])                 # duplicate neighbour
+    bad([0, 1, 2], [0, 1])                          # self loops
+    bad([0, 1, 2], [1, 5])                          # id out of range
+    bad([0, 1, 1], [1, 0])                          # row_ptr[n] != nnz
+    bad([1, 1, 2], [1, 0])                          # row_ptr[0] != 0
+    bad([0, 2, 1, 2], [1, 2])                       # not monotone
+    bad([0, 1, 1], [1])                             # odd entries, symmetric
+    bad([0, 1, 1, 1], [1], gpm.GPM_CSR_SYMMETRIC | gpm.GPM_VALIDATE)        # asymmetric
+    dag = gpm.GPM_CSR_DAG
+    assert gpm.validate_csr(np.array([0, 1, 2, 2]), np.array([1, 2]), dag | gpm.GPM_VALIDATE) == OK
+    bad([0, 1, 2], [1, 0], dag | gpm.GPM_VALIDATE)                          # both directions
+    bad([0, 1, 2, 3], [1, 2, 0], dag | gpm.GPM_VALIDATE)                    # 3-cycle
+    bad([0, 1, 2], [1, 0], dag | gpm.GPM_CSR_SYMMETRIC, INVAL)              # conflicting flags
+    bad([0, 1, 2], [1, 0], gpm.GPM_CSR_SYMMETRIC | gpm.GPM_PTRS_DEVICE, INVAL)
