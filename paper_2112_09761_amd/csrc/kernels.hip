@@ -289,6 +289,52 @@ __device__ __forceinline__ int select64(uint64_t x, int r) {
 // Sub-task `part` of `parts` handles its share of the local edges (i, j), so
 // the heaviest roots are spread over several waves (each rebuilds the local
 // graph, a small fraction of the root's work).
+// 5-clique pair phase of one local graph with W = WC words per row: local
+// edges p0 .. p1-1 (enumerated through the row-size prefix P), one per lane.
+template <bool CE, int WC, bool ORD, typename TP, typename TR>
+__device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t d, int32_t p0,
+                                               int32_t p1, ElemCounter& ec) {
+  const int l = lane_id();
+  uint64_t c = 0;
+  for (int32_t tb = p0; tb < p1; tb += 64) {
+    const int32_t t = tb + l;
+    if (t >= p1) continue;
+    const int32_t i = upper_bound(P + 1, d, t);
+    int32_t r = t - P[i];
+    const TR* Ri = R + (size_t)i * WC;
+    int32_t w = 0;
+    for (;; ++w) {
+      const int32_t pc = __popcll(Ri[w]);
+      if (r < pc) break;
+      r -= pc;
+    }
+    const int32_t j = w * 64 + select64(Ri[w], r);
+    const TR* Rj = R + (size_t)j * WC;
+    // ordered: R_j (and so M) has bits only above j, R_l only above l
+    const int jw = ORD ? ((j + 1) >> 6) : 0;
+    uint64_t M[WC];
+#pragma unroll
+    for (int x = 0; x < WC; ++x) M[x] = (x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
+    if (CE) ec.words += (uint64_t)(WC - jw);
+#pragma unroll
+    for (int x = 0; x < WC; ++x) {
+      uint64_t m = M[x];
+      while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1ull;
+        const int lidx = x * 64 + b;
+        const TR* Rl = R + (size_t)lidx * WC;
+        // words below x hold no bit above l when the lists are ordered
+#pragma unroll
+        for (int y = ORD ? x : 0; y < WC; ++y)
+          if (M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+        if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
+      }
+    }
+  }
+  return c;
+}
+
 template <bool CE, typename TL, typename TP, typename TR>
 __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
@@ -379,43 +425,18 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
     return c;
   }
   // k = 5: for every local edge (i, j) (one per lane) and every l in
-  // M = R_i & R_j add |M & R_l|; M stays in registers.
-  for (int32_t tb = p0; tb < p1; tb += 64) {
-    const int32_t t = tb + l;
-    if (t >= p1) continue;
-    int32_t i = upper_bound(P + 1, d, t);
-    int32_t r = t - P[i];
-    const TR* Ri = R + (size_t)i * W;
-    int32_t w = 0;
-    for (;; ++w) {
-      int32_t pc = __popcll(Ri[w]);
-      if (r < pc) break;
-      r -= pc;
-    }
-    const int32_t j = w * 64 + select64(Ri[w], r);
-    const TR* Rj = R + (size_t)j * W;
-    // ordered: R_j (and so M) has bits only above j, R_l only above l
-    const int jw = ordered ? ((j + 1) >> 6) : 0;
-    uint64_t M[kLgsMaxWords];
-#pragma unroll
-    for (int x = 0; x < kLgsMaxWords; ++x) M[x] = (x < W && x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
-    if (CE) ec.words += (uint64_t)(W - jw);
-#pragma unroll
-    for (int x = 0; x < kLgsMaxWords; ++x) {
-      if (x >= W) break;
-      uint64_t m = M[x];
-      while (m) {
-        const int b = __builtin_ctzll(m);
-        m &= m - 1ull;
-        const int lidx = x * 64 + b;
-        const int lw = ordered ? ((lidx + 1) >> 6) : 0;
-        const TR* Rl = R + (size_t)lidx * W;
-#pragma unroll
-        for (int y = 0; y < kLgsMaxWords; ++y)
-          if (y < W && y >= lw && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
-        if (CE) ec.words += (uint64_t)(W - lw);
-      }
-    }
+  // M = R_i & R_j add |M & R_l|; M stays in registers.  The word count W is a
+  // template constant so the inner loops carry no per-word range checks.
+  switch (W) {
+#define GPM_LGS5(WC) \
+  case WC:           \
+    return c + (ordered ? lgs_pairs5<CE, WC, true>(P, R, d, p0, p1, ec)    \
+                        : lgs_pairs5<CE, WC, false>(P, R, d, p0, p1, ec));
+    GPM_LGS5(1) GPM_LGS5(2) GPM_LGS5(3) GPM_LGS5(4) GPM_LGS5(5) GPM_LGS5(6) GPM_LGS5(7)
+    GPM_LGS5(8) GPM_LGS5(9) GPM_LGS5(10) GPM_LGS5(11) GPM_LGS5(12) GPM_LGS5(13)
+    GPM_LGS5(14) GPM_LGS5(15) GPM_LGS5(16)
+#undef GPM_LGS5
+    default: break;
   }
   return c;
 }
