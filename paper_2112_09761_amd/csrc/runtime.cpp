@@ -981,7 +981,8 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   if (stride > 0) {
     gpm_status s2 = gpm_frontier_waves((int64_t)frontier_budget, 1, stride, max_resident,
                                        max_resident, &waves);
-    if (s2) return fail(c, GPM_E_NOMEM, "frontier buffers do not fit the memory budget");
+    if (s2 || waves < kWavesPerBlock)
+      return fail(c, GPM_E_NOMEM, "frontier buffers do not fit the memory budget");
   }
   // 4-cycle wedge jobs: one zero-initialised counter array per wave
   int64_t zstride = 0;
