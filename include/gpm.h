@@ -140,6 +140,13 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *   "lgs_split"       1 = split the heaviest 5-clique roots across waves
  *   "leaf_cap"        generic DFS: last-level candidates whose leaf set is
  *                     at most this long are counted one per lane (0 = off)
+ *   "cycle4_algo"     edge-induced 4-cycles: 0/2 wedge aggregation, 1 the
+ *                     DFS plan (identical counts)
+ *   "wedge_mem"       bytes of device memory the 4-cycle counter arrays may
+ *                     use (default 16 GiB; fewer waves when exceeded)
+ *   "budget"          device memory budget in bytes (as in gpm_create)
+ *   "max_batch", "serve_slots", "max_pending"   serving limits
+ *   "tune_min_ms"     autotuner threshold (see "autotune")
  *   "count_elements"  1 = instrumented kernels count intersected elements
  *                     (slower; never used for timing)
  *   "autotune"        1 = on the first gpm_count of a (graph, pattern, mode)

@@ -10,6 +10,7 @@
 // counts stay in per-lane registers and are reduced once per job.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -1016,8 +1017,8 @@ gpm_persistent(KernelArgs a) {
 }
 
 __global__ void fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,7 +1058,7 @@ int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a, int
 
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream) {
   if (n <= 0) return 0;
-  int64_t blocks = (n + 255) / 256;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);  // grid-stride beyond
   hipLaunchKernelGGL(fill_u64, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, n,
                      v);
   return (int)hipGetLastError();

@@ -141,6 +141,7 @@ struct gpm_ctx {
   int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
   int64_t opt_tune_min_ms = 20;
+  int64_t opt_wedge_mem = int64_t(16) << 30;   // cap of the 4-cycle counter arrays
   // autotuner cache: (graph, pattern, mode) -> tuned knob values
   std::map<std::string, std::vector<std::pair<std::string, int64_t>>> tuned;
   bool tuning = false;
@@ -991,7 +992,8 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   zstride = (int64_t)align_up((size_t)zstride, 64);
   if (zstride) {
     waves = std::min<int64_t>(waves, kWedgeWaves(c));
-    const int64_t left = (int64_t)frontier_budget - waves * stride * 4;
+    const int64_t left = std::min<int64_t>((int64_t)frontier_budget - waves * stride * 4,
+                                           c->opt_wedge_mem);
     const int64_t zw = left > 0 ? left / (zstride * 4) : 0;
     if (zw < kWavesPerBlock) return fail(c, GPM_E_NOMEM, "wedge counters do not fit the memory budget");
     waves = std::min(waves, zw);
@@ -1427,6 +1429,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;
+  else if (k == "wedge_mem") { if (v < (1 << 20)) return fail(c, GPM_E_INVAL, "wedge_mem >= 1 MiB"); c->opt_wedge_mem = v; }
   else if (k == "tune_min_ms") { if (v < 0) return fail(c, GPM_E_INVAL, "tune_min_ms >= 0"); c->opt_tune_min_ms = v; }
   else if (k == "max_batch") { if (v < 1) return fail(c, GPM_E_INVAL, "max_batch >= 1"); c->opt_max_batch = v; }
   else if (k == "serve_slots") { if (v < 1 || v > kMaxSlots) return fail(c, GPM_E_INVAL, "serve_slots 1..4"); c->opt_serve_slots = v; }
