@@ -61,6 +61,7 @@ def algorithmic_bytes(st):
 
 def cpu_baseline_clique4(g, elements4):
     from oracle import pyoracle
+    progress("CPU oracle baseline (4-clique)")
     t = time.perf_counter()
     c = pyoracle.cliques(g, 4, 1)
     dt = time.perf_counter() - t
@@ -74,8 +75,10 @@ def cpu_baseline_clique4(g, elements4):
 def run_clique(args, ctx, torch):
     from paper_2112_09761_amd import synth
     g = synth.workload_rmat_s20()
+    progress("graph generated")
     gid = ctx.load(g)
     info = ctx.graph_info(gid)  # forces the degree orientation (untimed)
+    progress("graph loaded and prepared")
     # instrumented passes (never timed).  The work per count is defined by
     # the paper's sorted-list plan (edge kernel, clique_algo=1): the
     # intersected elements it executes.  The timed kernel (local-graph
@@ -92,6 +95,7 @@ def run_clique(args, ctx, torch):
         ctx.count(gid, (k, [(i, j) for i in range(k) for j in range(i + 1, k)]))
         inst_lgs[k] = ctx.stats()
     ctx.set_option("count_elements", 0)
+    progress("instrumented passes done")
     pats = {k: (k, [(i, j) for i in range(k) for j in range(i + 1, k)]) for k in (4, 5)}
     if not args.no_autotune:
         ctx.set_option("autotune", 1)   # the first (warm-up) call of each count tunes
@@ -184,10 +188,18 @@ def _gen_pool(i):
     return g.n, g.row_ptr, g.col
 
 
-def gen_parallel(fn, count, procs=8):
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gen_parallel(fn, count, procs=16):
     import multiprocessing as mp
+    out = [None] * count
     with mp.get_context("spawn").Pool(procs) as pool:
-        return pool.map(fn, range(count), chunksize=1)
+        for i, r in enumerate(pool.imap(fn, range(count), chunksize=1)):
+            out[i] = r
+            progress(f"generated graph {i + 1}/{count} (n={r[0]})")
+    return out
 
 
 def run_batch(args, ctx, torch):
@@ -200,6 +212,7 @@ def run_batch(args, ctx, torch):
     ids = [ctx.load_csr(rp, col) for n, rp, col in graphs]
     for gid in ids:
         ctx.graph_info(gid)
+    progress("batch graphs loaded and prepared")
     qs = [gpm.motif_query(gid, 4) for gid in ids]
     ctx.count_batch(qs)  # preparation of every graph (untimed) and warm-up
     for gid in ids[:8]:
@@ -246,6 +259,7 @@ def run_serve(args, ctx, torch):
     graphs = gen_parallel(_gen_pool, n_pool)
     gen_s = time.perf_counter() - t
     ids = [ctx.load_csr(rp, col) for n, rp, col in graphs]
+    progress("pool loaded")
     # every (graph, pattern) pair alone, warm: reference results and costs
     alone, cost = {}, {}
     for gi, gid in enumerate(ids):
@@ -254,6 +268,8 @@ def run_serve(args, ctx, torch):
             t = time.perf_counter()
             alone[(gi, pi)] = ctx.count(gid, name, mode)
             cost[(gi, pi)] = time.perf_counter() - t
+        progress(f"alone pass graph {gi + 1}/{n_pool}: "
+                 f"{[round(cost[(gi, p)] * 1e3, 1) for p in range(len(SERVE_PATTERNS))]} ms")
     rng = np.random.default_rng(20_000)
 
     def draw(n):
@@ -271,6 +287,7 @@ def run_serve(args, ctx, torch):
     res = [ctx.wait(tk)[0] for tk in tickets]
     mu = n_q / (time.perf_counter() - t)
     mix_ok = all(r == alone[q] for r, q in zip(res, sat))
+    progress(f"saturated throughput {mu:.1f} queries/s, results identical: {mix_ok}")
     loads = []
     for frac in (0.3, 0.6, 0.9):
         lam = frac * mu
@@ -296,6 +313,7 @@ def run_serve(args, ctx, torch):
                 time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - t0), 0.001)))
         span = time.perf_counter() - t0
         la = np.array(lat) * 1e3
+        progress(f"load {frac}: {n_q / span:.1f} queries/s")
         loads.append({"offered_qps": lam, "achieved_qps": n_q / span,
                       "p50_ms": float(np.percentile(la, 50)),
                       "p99_ms": float(np.percentile(la, 99)), "queries": n_q})
