@@ -254,7 +254,7 @@ def run_serve(args, ctx, torch):
     import numpy as np
     from paper_2112_09761_amd import gpm
     n_pool = int(os.environ.get("GPM_SERVE_POOL", "32"))
-    n_q = int(os.environ.get("GPM_SERVE_QUERIES", "200"))
+    n_q = int(os.environ.get("GPM_SERVE_QUERIES", "100"))
     t = time.perf_counter()
     graphs = gen_parallel(_gen_pool, n_pool)
     gen_s = time.perf_counter() - t
@@ -264,12 +264,10 @@ def run_serve(args, ctx, torch):
     alone, cost = {}, {}
     for gi, gid in enumerate(ids):
         for pi, (name, mode) in enumerate(SERVE_PATTERNS):
-            ctx.count(gid, name, mode)
             t = time.perf_counter()
             alone[(gi, pi)] = ctx.count(gid, name, mode)
             cost[(gi, pi)] = time.perf_counter() - t
-        progress(f"alone pass graph {gi + 1}/{n_pool}: "
-                 f"{[round(cost[(gi, p)] * 1e3, 1) for p in range(len(SERVE_PATTERNS))]} ms")
+            progress(f"alone graph {gi + 1}/{n_pool} {name}: {cost[(gi, pi)] * 1e3:.1f} ms")
     rng = np.random.default_rng(20_000)
 
     def draw(n):
@@ -284,7 +282,11 @@ def run_serve(args, ctx, torch):
     sat = draw(n_q)
     t = time.perf_counter()
     tickets = [ctx.submit(query(gi, pi)) for gi, pi in sat]
-    res = [ctx.wait(tk)[0] for tk in tickets]
+    res = []
+    for i, tk in enumerate(tickets):
+        res.append(ctx.wait(tk)[0])
+        if (i + 1) % 10 == 0:
+            progress(f"saturated: {i + 1}/{n_q} done")
     mu = n_q / (time.perf_counter() - t)
     mix_ok = all(r == alone[q] for r, q in zip(res, sat))
     progress(f"saturated throughput {mu:.1f} queries/s, results identical: {mix_ok}")
@@ -309,6 +311,8 @@ def run_serve(args, ctx, torch):
                     i = pending.pop(tk)
                     lat[i] = (time.perf_counter() - t0) - arrive[i]
                     mix_ok &= out[0] == alone[qs[i]]
+                    if sum(x is not None for x in lat) % 10 == 0:
+                        progress(f"load {frac}: {sum(x is not None for x in lat)}/{n_q} done")
             if not pending and nxt < n_q:
                 time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - t0), 0.001)))
         span = time.perf_counter() - t0

@@ -61,7 +61,7 @@ constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
 constexpr uint32_t kKindCycleWedge = 1u << kJobCycleWedge;
 constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg |
                               kKindCliqueLgs | kKindCycleWedge;
-constexpr int kLgsMaxVertices = 1024;   // local graphs handled by the bitmap kernel
+constexpr int kLgsMaxVertices = 2048;   // local graphs handled by the bitmap kernel
 
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
 // root tasks) triple with its own result slot.

@@ -269,7 +269,7 @@ __device__ __forceinline__ uint64_t clique_edge(const int64_t* __restrict__ rp,
 // ANDed rows.  One wave per root vertex.
 // ---------------------------------------------------------------------------
 
-constexpr int kLgsMaxWords = 16;  // local graphs of up to 1024 vertices
+constexpr int kLgsMaxWords = kLgsMaxVertices / 64;  // words per bitmap row
 
 // position of the r-th (0-based) set bit of x (r < popcount(x))
 __device__ __forceinline__ int select64(uint64_t x, int r) {
@@ -317,18 +317,17 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
 #pragma unroll
     for (int x = 0; x < WC; ++x) M[x] = (x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
     if (CE) ec.words += (uint64_t)(WC - jw);
-#pragma unroll
-    for (int x = 0; x < WC; ++x) {
-      uint64_t m = M[x];
+    // outer loop over the words of M (reloaded: dynamic register indexing
+    // would go to scratch), inner loop unrolled over registers
+    for (int x = jw; x < WC; ++x) {
+      uint64_t m = Ri[x] & Rj[x];
       while (m) {
         const int b = __builtin_ctzll(m);
         m &= m - 1ull;
-        const int lidx = x * 64 + b;
-        const TR* Rl = R + (size_t)lidx * WC;
-        // words below x hold no bit above l when the lists are ordered
+        const TR* Rl = R + (size_t)(x * 64 + b) * WC;
 #pragma unroll
-        for (int y = ORD ? x : 0; y < WC; ++y)
-          if (M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+        for (int y = 0; y < WC; ++y)
+          if ((!ORD || y >= x) && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
         if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
       }
     }
@@ -428,16 +427,50 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   // k = 5: for every local edge (i, j) (one per lane) and every l in
   // M = R_i & R_j add |M & R_l|; M stays in registers.  The word count W is a
   // template constant so the inner loops carry no per-word range checks.
-  switch (W) {
+  if (!CE && ordered) {
+    switch (W) {
 #define GPM_LGS5(WC) \
   case WC:           \
-    return c + (ordered ? lgs_pairs5<CE, WC, true>(P, R, d, p0, p1, ec)    \
-                        : lgs_pairs5<CE, WC, false>(P, R, d, p0, p1, ec));
-    GPM_LGS5(1) GPM_LGS5(2) GPM_LGS5(3) GPM_LGS5(4) GPM_LGS5(5) GPM_LGS5(6) GPM_LGS5(7)
-    GPM_LGS5(8) GPM_LGS5(9) GPM_LGS5(10) GPM_LGS5(11) GPM_LGS5(12) GPM_LGS5(13)
-    GPM_LGS5(14) GPM_LGS5(15) GPM_LGS5(16)
+    return c + lgs_pairs5<CE, WC, true>(P, R, d, p0, p1, ec);
+      GPM_LGS5(1) GPM_LGS5(2) GPM_LGS5(3) GPM_LGS5(4) GPM_LGS5(5) GPM_LGS5(6) GPM_LGS5(7)
+      GPM_LGS5(8) GPM_LGS5(9) GPM_LGS5(10) GPM_LGS5(11) GPM_LGS5(12) GPM_LGS5(13)
+      GPM_LGS5(14) GPM_LGS5(15) GPM_LGS5(16) GPM_LGS5(17) GPM_LGS5(18) GPM_LGS5(19)
+      GPM_LGS5(20) GPM_LGS5(21) GPM_LGS5(22) GPM_LGS5(23) GPM_LGS5(24) GPM_LGS5(25)
+      GPM_LGS5(26) GPM_LGS5(27) GPM_LGS5(28) GPM_LGS5(29) GPM_LGS5(30) GPM_LGS5(31)
+      GPM_LGS5(32)
 #undef GPM_LGS5
-    default: break;
+      default: break;
+    }
+  }
+  // lists in arbitrary order (a DAG given by the caller): words recomputed
+  for (int32_t tb = p0; tb < p1; tb += 64) {
+    const int32_t t = tb + l;
+    if (t >= p1) continue;
+    const int32_t i = upper_bound(P + 1, d, t);
+    int32_t r = t - P[i];
+    const TR* Ri = R + (size_t)i * W;
+    int32_t w = 0;
+    for (;; ++w) {
+      const int32_t pc = __popcll(Ri[w]);
+      if (r < pc) break;
+      r -= pc;
+    }
+    const int32_t j = w * 64 + select64(Ri[w], r);
+    const TR* Rj = R + (size_t)j * W;
+    // (instrumented counts follow the ordered path's word ranges)
+    const int32_t jw = ordered ? ((j + 1) >> 6) : 0;
+    if (CE) ec.words += (uint64_t)(W - jw);
+    for (int32_t x = jw; x < W; ++x) {
+      uint64_t m = Ri[x] & Rj[x];
+      while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1ull;
+        const TR* Rl = R + (size_t)(x * 64 + b) * W;
+        const int32_t y0 = ordered ? x : 0;
+        for (int32_t y = y0; y < W; ++y) c += (uint64_t)__popcll(Ri[y] & Rj[y] & Rl[y]);
+        if (CE) ec.words += (uint64_t)(W - y0);
+      }
+    }
   }
   return c;
 }
