@@ -187,6 +187,11 @@ gpm_status gpm_load_csr(gpm_ctx *ctx, int64_t n, int64_t nnz,
 gpm_status gpm_validate_csr(int64_t n, int64_t nnz, const int64_t *row_ptr,
                             const int32_t *col, uint32_t flags);
 
+/* Run every preparation step now (relabelling by degree, orientation, root
+ * task lists) instead of lazily at the first count that needs it, e.g. for
+ * a serving pool whose queries must not pay for preparation. */
+gpm_status gpm_prepare(gpm_ctx *ctx, int32_t graph_id);
+
 gpm_status gpm_unload(gpm_ctx *ctx, int32_t graph_id);
 
 gpm_status gpm_graph_info(gpm_ctx *ctx, int32_t graph_id, gpm_graph_meta *out);

@@ -317,18 +317,35 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
 #pragma unroll
     for (int x = 0; x < WC; ++x) M[x] = (x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
     if (CE) ec.words += (uint64_t)(WC - jw);
-    // outer loop over the words of M (reloaded: dynamic register indexing
-    // would go to scratch), inner loop unrolled over registers
-    for (int x = jw; x < WC; ++x) {
-      uint64_t m = Ri[x] & Rj[x];
-      while (m) {
-        const int b = __builtin_ctzll(m);
-        m &= m - 1ull;
-        const TR* Rl = R + (size_t)(x * 64 + b) * WC;
+    if constexpr (WC <= 16) {
+      // both loops unrolled: every word index is static
 #pragma unroll
-        for (int y = 0; y < WC; ++y)
-          if ((!ORD || y >= x) && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
-        if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
+      for (int x = 0; x < WC; ++x) {
+        uint64_t m = M[x];
+        while (m) {
+          const int b = __builtin_ctzll(m);
+          m &= m - 1ull;
+          const TR* Rl = R + (size_t)(x * 64 + b) * WC;
+#pragma unroll
+          for (int y = ORD ? x : 0; y < WC; ++y)
+            if (M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+          if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
+        }
+      }
+    } else {
+      // wide rows: outer loop over the words of M (reloaded, since dynamic
+      // register indexing would go to scratch), inner loop unrolled
+      for (int x = jw; x < WC; ++x) {
+        uint64_t m = Ri[x] & Rj[x];
+        while (m) {
+          const int b = __builtin_ctzll(m);
+          m &= m - 1ull;
+          const TR* Rl = R + (size_t)(x * 64 + b) * WC;
+#pragma unroll
+          for (int y = 0; y < WC; ++y)
+            if ((!ORD || y >= x) && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+          if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
+        }
       }
     }
   }

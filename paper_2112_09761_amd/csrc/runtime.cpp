@@ -1495,6 +1495,23 @@ gpm_status gpm_unload(gpm_ctx* c, int32_t id) {
   return GPM_OK;
 }
 
+gpm_status gpm_prepare(gpm_ctx* c, int32_t id) {
+  if (!c) return GPM_E_INVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Graph* g = find_graph(c, id);
+  if (!g) return fail(c, GPM_E_INVAL, "unknown graph id");
+  gpm_status st = ensure_dag(c, *g);
+  if (st) return st;
+  st = ensure_lgs(c, *g, c->opt_lgs_max);
+  if (st) return st;
+  if (g->dag_only) return GPM_OK;
+  st = ensure_ren(c, *g);
+  if (st) return st;
+  st = ensure_lower(c, *g);
+  if (st) return st;
+  return ensure_wedge(c, *g, kWedgeWaves(c));
+}
+
 gpm_status gpm_graph_info(gpm_ctx* c, int32_t id, gpm_graph_meta* out) {
   if (!c || !out) return GPM_E_INVAL;
   Graph* g = find_graph(c, id);

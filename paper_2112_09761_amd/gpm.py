@@ -40,7 +40,7 @@ EXPORTS = [
     "gpm_load_csr", "gpm_unload", "gpm_graph_info", "gpm_pattern_clique",
     "gpm_pattern_named", "gpm_pattern_from_edges", "gpm_plan", "gpm_frontier_waves",
     "gpm_count", "gpm_motifs", "gpm_count_batch", "gpm_submit", "gpm_poll", "gpm_wait",
-    "gpm_inflight", "gpm_validate_csr",
+    "gpm_inflight", "gpm_validate_csr", "gpm_prepare",
 ]
 
 
@@ -124,6 +124,7 @@ def lib():
         L.gpm_wait.argtypes = [c_vp, c_i64, c_i64, P(c_u64)]
         L.gpm_inflight.argtypes = [c_vp, P(c_i64)]
         L.gpm_validate_csr.argtypes = [c_i64, c_i64, c_vp, c_vp, ctypes.c_uint32]
+        L.gpm_prepare.argtypes = [c_vp, c_i32]
         for name in EXPORTS:
             if name != "gpm_last_error":
                 getattr(L, name).restype = ctypes.c_int32
@@ -294,6 +295,9 @@ class Context:
     def load(self, g, flags: int = GPM_CSR_SYMMETRIC) -> int:
         """Load a synth.CSR graph."""
         return self.load_csr(g.row_ptr, g.col, flags)
+
+    def prepare(self, graph_id: int):
+        self._ck(lib().gpm_prepare(self._h, graph_id))
 
     def unload(self, graph_id: int):
         self._ck(lib().gpm_unload(self._h, graph_id))

@@ -221,6 +221,7 @@ def test_edge_cases(ctx):
     ctx.unload(gid)
     k3 = synth.complete(3)
     gid = ctx.load(k3)
+    ctx.prepare(gid)
     assert ctx.count(gid, "clique4") == 0
     assert ctx.count(gid, "edge") == 3
     assert ctx.count(gid, "triangle") == 1
