@@ -112,6 +112,7 @@ struct Slot {
   bool busy = false;
   size_t frontier_bytes_in_use = 0;
   std::vector<QueryWork> queries;
+  std::vector<std::string> qkeys;  // serving: cost keys of the launch's queries
   int n_jobs = 0;
   int n_launch = 0;
   size_t counters_off = 0;   // word offset of the instrumentation counters in h_res
@@ -150,6 +151,8 @@ struct gpm_ctx {
   // serving
   std::deque<Pending> pending;
   std::unordered_map<int64_t, std::array<uint64_t, 6>> done;
+  std::unordered_map<std::string, double> qcost;  // kernel ms of queries run alone
+  int64_t opt_serve_light_ms = 50;
   int64_t next_ticket = 1;
   size_t serve_frontier_in_use = 0;
 };
@@ -1213,7 +1216,19 @@ static int n_serve_slots(const gpm_ctx* c) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSlots, c->opt_serve_slots));
 }
 
+static std::string query_key(const gpm_query& q) {
+  std::string k = std::to_string(q.graph_id) + ":" + std::to_string(q.kind) + ":" +
+                  std::to_string(q.mode_or_k);
+  if (q.kind == GPM_QUERY_COUNT)
+    for (int i = 0; i < 2 * q.pattern.n_edges; ++i) k += "," + std::to_string(q.pattern.edges[i]);
+  return k;
+}
+
 // Collect finished launches, then admit pending queries into free slots.
+// Continuous batching with cost awareness: a query whose cost is unknown or
+// above serve_light_ms (measured when it last ran alone) gets a launch of
+// its own, so light queries never wait behind it; light queries are batched
+// together, up to max_batch per launch, in arrival order.
 static gpm_status progress(gpm_ctx* c) {
   const int ns = n_serve_slots(c);
   for (int i = 1; i <= ns; ++i) {
@@ -1223,29 +1238,42 @@ static gpm_status progress(gpm_ctx* c) {
     if (e == hipErrorNotReady) continue;
     if (e != hipSuccess) return fail(c, GPM_E_DEVICE, std::string("serving launch: ") + hipGetErrorString(e));
     HIP_TRY(c, hipStreamSynchronize(s.stream));  // result copy queued after ev1
+    if (s.queries.size() == 1 && s.n_launch > 0) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, s.ev0, s.ev1) == hipSuccess) c->qcost[s.qkeys[0]] = ms;
+    }
     for (auto& qw : s.queries) {
       std::array<uint64_t, 6> r{};
       finish_query(qw, s.h_res, r.data());
       c->done[qw.ticket] = r;
     }
     s.queries.clear();
+    s.qkeys.clear();
     s.busy = false;
     s.zero_dirty = false;
     c->serve_frontier_in_use -= s.frontier_bytes_in_use;
     s.frontier_bytes_in_use = 0;
   }
+  auto light = [&](const gpm_query& q) {
+    auto it = c->qcost.find(query_key(q));
+    return it != c->qcost.end() && it->second <= (double)c->opt_serve_light_ms;
+  };
   for (int i = 1; i <= ns && !c->pending.empty(); ++i) {
     Slot& s = c->slots[i];
     if (s.busy) continue;
     gpm_status st = slot_init(c, s, nullptr);
     if (st) return st;
     size_t avail = c->budget > c->serve_frontier_in_use ? c->budget - c->serve_frontier_in_use : 0;
-    // continuous batching: every pending query (up to max_batch) joins this launch
     JobPlanSet js;
     std::vector<QueryWork> qs;
-    int taken = 0;
-    while (!c->pending.empty() && taken < c->opt_max_batch) {
-      Pending pq = c->pending.front();
+    std::vector<std::string> keys;
+    const bool batchable = light(c->pending.front().q);
+    for (auto it = c->pending.begin(); it != c->pending.end() && (int64_t)qs.size() < c->opt_max_batch;) {
+      if (!qs.empty() && (!batchable || !light(it->q))) {
+        ++it;
+        continue;
+      }
+      Pending pq = *it;
       QueryWork qw;
       size_t before = js.jobs.size();
       size_t pbefore = js.plans.size();
@@ -1258,7 +1286,7 @@ static gpm_status progress(gpm_ctx* c) {
         std::array<uint64_t, 6> r;
         r.fill(~0ull);
         c->done[pq.ticket] = r;
-        c->pending.pop_front();
+        it = c->pending.erase(it);
         continue;
       }
       // admission by frontier memory: the group's per-wave region must leave
@@ -1266,7 +1294,7 @@ static gpm_status progress(gpm_ctx* c) {
       int64_t stride = 0;
       for (auto w : js.need_words) stride = std::max(stride, w);
       size_t min_bytes = (size_t)align_up((size_t)stride, 64) * 4 * (size_t)(c->cus);
-      if (taken > 0 && min_bytes > avail) {
+      if (!qs.empty() && min_bytes > avail) {
         js.jobs.resize(before);
         js.need_words.resize(before);
         js.plans.resize(pbefore);
@@ -1274,12 +1302,12 @@ static gpm_status progress(gpm_ctx* c) {
       }
       qw.ticket = pq.ticket;
       qs.push_back(qw);
-      c->pending.pop_front();
-      ++taken;
+      keys.push_back(query_key(pq.q));
+      it = c->pending.erase(it);
+      if (!batchable) break;
     }
     if (qs.empty()) continue;
-    bool any_jobs = !js.jobs.empty();
-    if (!any_jobs) {
+    if (js.jobs.empty()) {
       for (auto& qw : qs) {
         std::array<uint64_t, 6> r{};
         finish_query(qw, nullptr, r.data());
@@ -1291,6 +1319,7 @@ static gpm_status progress(gpm_ctx* c) {
     st = launch_group(c, s, js, false, avail, &used);
     if (st) return st;
     s.queries = qs;
+    s.qkeys = keys;
     s.busy = true;
     s.frontier_bytes_in_use = used;
     c->serve_frontier_in_use += used;
@@ -1433,6 +1462,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "tune_min_ms") { if (v < 0) return fail(c, GPM_E_INVAL, "tune_min_ms >= 0"); c->opt_tune_min_ms = v; }
   else if (k == "max_batch") { if (v < 1) return fail(c, GPM_E_INVAL, "max_batch >= 1"); c->opt_max_batch = v; }
   else if (k == "serve_slots") { if (v < 1 || v > kMaxSlots) return fail(c, GPM_E_INVAL, "serve_slots 1..4"); c->opt_serve_slots = v; }
+  else if (k == "serve_light_ms") { if (v < 0) return fail(c, GPM_E_INVAL, "serve_light_ms >= 0"); c->opt_serve_light_ms = v; }
   else if (k == "max_pending") { if (v < 1) return fail(c, GPM_E_INVAL, "max_pending >= 1"); c->opt_max_pending = v; }
   else if (k == "budget") { if (v < 0) return fail(c, GPM_E_INVAL, "budget >= 0"); c->budget = (size_t)v; }
   else return fail(c, GPM_E_INVAL, "unknown option " + k);
