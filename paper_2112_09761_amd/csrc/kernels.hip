@@ -317,6 +317,8 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
 #pragma unroll
     for (int x = 0; x < WC; ++x) M[x] = (x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
     if (CE) ec.words += (uint64_t)(WC - jw);
+    // the pair's count fits 32 bits (|M| * d < 2^22): popcount-accumulate
+    uint32_t cp = 0;
     if constexpr (WC <= 16) {
       // both loops unrolled: every word index is static
 #pragma unroll
@@ -327,8 +329,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
           m &= m - 1ull;
           const TR* Rl = R + (size_t)(x * 64 + b) * WC;
 #pragma unroll
-          for (int y = ORD ? x : 0; y < WC; ++y)
-            if (M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+          for (int y = ORD ? x : 0; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
           if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
         }
       }
@@ -343,11 +344,12 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
           const TR* Rl = R + (size_t)(x * 64 + b) * WC;
 #pragma unroll
           for (int y = 0; y < WC; ++y)
-            if ((!ORD || y >= x) && M[y] != 0ull) c += (uint64_t)__popcll(M[y] & Rl[y]);
+            if (!ORD || y >= x) cp += (uint32_t)__popcll(M[y] & Rl[y]);
           if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
         }
       }
     }
+    c += cp;
   }
   return c;
 }
@@ -436,7 +438,9 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       const TR* Rj = R + (size_t)j * W;
       // ordered: R_j has bits only above j
       const int32_t x0 = ordered ? ((j + 1) >> 6) : 0;
-      for (int32_t x = x0; x < W; ++x) c += (uint64_t)__popcll(Ri[x] & Rj[x]);
+      uint32_t cp = 0;
+      for (int32_t x = x0; x < W; ++x) cp += (uint32_t)__popcll(Ri[x] & Rj[x]);
+      c += cp;
       if (CE) ec.words += (uint64_t)(W - x0);
     }
     return c;
