@@ -26,6 +26,16 @@ HBM_PEAK_GBS = 8000.0
 # v_bcnt_u32_b32 per word; 256 CUs x 64 int32 lanes/clock x 2.4 GHz / 4
 WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 
+# HBM traffic of the 5-clique launch: two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch) each scaled by what the same counter reads for
+# a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
+# for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
+# the kernel sources they were taken on only; any change to them reports null.
+TRAFFIC = {"sources_sha256": "c08969bdba77d4942b9a1510e56fbdf3cda088b0bca04f33cdea0e52edc5ab2f",
+           "fetch_kib": 1.2477e7, "write_kib": 2.0803e7,
+           "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -57,6 +67,23 @@ def algorithmic_bytes(st):
     # 4 B per intersected element, 16 B per neighbour-list fetch (row offsets),
     # 4 B per frontier element written
     return 4 * st["elements"] + 16 * st["list_fetches"] + 4 * st["frontier_written"]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_09761_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per 5-clique launch from the counters, or None if stale."""
+    if not TRAFFIC["sources_sha256"] or TRAFFIC["sources_sha256"] != sources_sha256():
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] +
+                     TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
 
 
 def cpu_baseline_clique4(g, elements4):
@@ -142,7 +169,7 @@ def run_clique(args, ctx, torch):
         "roofline": {"bound": "alu", "kernel": "gpm_persistent<local-graph clique> (5-clique launch)",
                      "achieved": achieved, "peak": WORD_OP_PEAK_TOPS,
                      "unit": "TOP/s (64-bit AND+popcount word ops)",
-                     "frac": achieved / WORD_OP_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / WORD_OP_PEAK_TOPS, "traffic": measured_traffic(),
                      "word_ops_per_launch": words5,
                      "hbm_view": {"algorithmic_bytes_per_launch": b5, "achieved_GBs": hbm_gbs,
                                   "peak_GBs": HBM_PEAK_GBS, "frac": hbm_gbs / HBM_PEAK_GBS}},
