@@ -133,11 +133,16 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     given (0); counts are identical either way
  *   "clique_algo"     0 auto (local-graph bitmaps for cliques up to 5
  *                     vertices), 1 sorted-list edge kernel, 2 bitmaps
- *   "lgs_tile"        local graphs up to this many vertices stay in LDS
- *                     (64..256; larger ones use HBM rows)
- *   "lgs_max"         roots with more out-neighbours (64..1024) use the
+ *   "lgs_tile"        local graphs up to this many vertices stay in one
+ *                     wave's LDS (64..256, default 128)
+ *   "lgs_block"       1 (default) = larger local graphs that fit a
+ *                     workgroup's LDS (up to 1024 vertices, fewer when the
+ *                     device's per-workgroup LDS is smaller) are searched by
+ *                     a whole workgroup each; 0 = by one wave, rows in HBM
+ *   "lgs_max"         roots with more out-neighbours (64..2048) use the
  *                     edge kernel
- *   "lgs_split"       1 = split the heaviest 5-clique roots across waves
+ *   "lgs_split"       1 = split the heaviest roots (5-cliques per wave,
+ *                     4- and 5-cliques per workgroup) into sub-tasks
  *   "leaf_cap"        generic DFS: last-level candidates whose leaf set is
  *                     at most this long are counted one per lane (0 = off)
  *   "cycle4_algo"     edge-induced 4-cycles: 0/2 wedge aggregation, 1 the

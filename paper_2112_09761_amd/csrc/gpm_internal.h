@@ -51,6 +51,8 @@ enum JobKind : int32_t {
   kJobVertexDeg = 4,   // per-vertex degree terms
   kJobCliqueLgs = 5,   // k-clique (k = 3..5) by local graph search with bitmaps
   kJobCycleWedge = 6,  // edge-induced 4-cycles by wedge aggregation
+  kJobCliqueLgsBlock = 7,  // k-clique (k = 3..5): the local graph of one large
+                           // root shared by a whole workgroup (own kernel)
 };
 
 constexpr uint32_t kKindClique = 1u << kJobClique;
@@ -59,9 +61,13 @@ constexpr uint32_t kKindEdgeTri = 1u << kJobEdgeTri;
 constexpr uint32_t kKindVertexDeg = 1u << kJobVertexDeg;
 constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
 constexpr uint32_t kKindCycleWedge = 1u << kJobCycleWedge;
+constexpr uint32_t kKindCliqueLgsBlock = 1u << kJobCliqueLgsBlock;
+// kinds of the per-wave persistent kernel (the workgroup kernel has its own)
 constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg |
                               kKindCliqueLgs | kKindCycleWedge;
 constexpr int kLgsMaxVertices = 2048;   // local graphs handled by the bitmap kernel
+constexpr int kBlockWaves = 16;         // workgroup of the large-root kernel (1024 threads)
+constexpr int kLgsBlockMaxVertices = kBlockWaves * 64;  // one vertex per thread in its scans
 
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
 // root tasks) triple with its own result slot.
@@ -111,9 +117,20 @@ __host__ __device__ inline int64_t lgs_tile_words(int64_t T) {
   return lgs_rows_offset(T) + 2 * T * ((T + 63) / 64);
 }
 
-// Host-side launcher (kernels.hip).  Returns a hipError_t as int.
+// Workgroup local graph of d vertices, in int32 words: L[d] | P[d + 1] |
+// (pad to 8 B) | S[d] int64 (offsets of the out-lists of L) | R[d * ceil(d / 64)]
+// uint64.  Sized per root; the launch provides room for its largest root.
+__host__ __device__ inline int64_t lgs_block_s_offset(int64_t d) { return (2 * d + 2) & ~int64_t(1); }
+__host__ __device__ inline int64_t lgs_block_r_offset(int64_t d) { return lgs_block_s_offset(d) + 2 * d; }
+__host__ __device__ inline int64_t lgs_block_words(int64_t d) {
+  return lgs_block_r_offset(d) + 2 * d * ((d + 63) / 64);
+}
+
+// Host-side launchers (kernels.hip).  Return a hipError_t as int.
 int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a,
                       int blocks, size_t lds_bytes, void* stream);
+int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max_blocks,
+                     size_t lds_bytes, void* stream);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
 
 }  // namespace gpm

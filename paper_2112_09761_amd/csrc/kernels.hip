@@ -291,15 +291,14 @@ __device__ __forceinline__ int select64(uint64_t x, int r) {
 // the heaviest roots are spread over several waves (each rebuilds the local
 // graph, a small fraction of the root's work).
 // 5-clique pair phase of one local graph with W = WC words per row: local
-// edges p0 .. p1-1 (enumerated through the row-size prefix P), one per lane.
+// edges p0 .. p1-1 (enumerated through the row-size prefix P), one per
+// thread: this thread takes p0 + first, p0 + first + step, ...
 template <bool CE, int WC, bool ORD, typename TP, typename TR>
 __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t d, int32_t p0,
-                                               int32_t p1, ElemCounter& ec) {
-  const int l = lane_id();
+                                               int32_t p1, int32_t first, int32_t step,
+                                               ElemCounter& ec) {
   uint64_t c = 0;
-  for (int32_t tb = p0; tb < p1; tb += 64) {
-    const int32_t t = tb + l;
-    if (t >= p1) continue;
+  for (int32_t t = p0 + first; t < p1; t += step) {
     const int32_t i = upper_bound(P + 1, d, t);
     int32_t r = t - P[i];
     const TR* Ri = R + (size_t)i * WC;
@@ -452,7 +451,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
     switch (W) {
 #define GPM_LGS5(WC) \
   case WC:           \
-    return c + lgs_pairs5<CE, WC, true>(P, R, d, p0, p1, ec);
+    return c + lgs_pairs5<CE, WC, true>(P, R, d, p0, p1, l, 64, ec);
       GPM_LGS5(1) GPM_LGS5(2) GPM_LGS5(3) GPM_LGS5(4) GPM_LGS5(5) GPM_LGS5(6) GPM_LGS5(7)
       GPM_LGS5(8) GPM_LGS5(9) GPM_LGS5(10) GPM_LGS5(11) GPM_LGS5(12) GPM_LGS5(13)
       GPM_LGS5(14) GPM_LGS5(15) GPM_LGS5(16) GPM_LGS5(17) GPM_LGS5(18) GPM_LGS5(19)
@@ -487,6 +486,155 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
         const int b = __builtin_ctzll(m);
         m &= m - 1ull;
         const TR* Rl = R + (size_t)(x * 64 + b) * W;
+        const int32_t y0 = ordered ? x : 0;
+        for (int32_t y = y0; y < W; ++y) c += (uint64_t)__popcll(Ri[y] & Rj[y] & Rl[y]);
+        if (CE) ec.words += (uint64_t)(W - y0);
+      }
+    }
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// local graphs of large roots: one workgroup of kBlockWaves waves per root
+// ---------------------------------------------------------------------------
+
+// Inclusive scan of one value per thread over the workgroup; `total` gets
+// the sum.  tmp: kBlockWaves words of LDS.  Contains workgroup barriers.
+__device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* tmp, int32_t& total) {
+  const int w = threadIdx.x >> 6;
+  const int32_t inc = wave_incl_scan(v);
+  if (lane_id() == 63) tmp[w] = inc;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlockWaves; ++i) {
+    const int32_t x = tmp[i];
+    off += (i < w) ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return off + inc;
+}
+
+// The same local-graph search as clique_lgs, for a root u with
+// d <= kLgsBlockMaxVertices out-neighbours, with every step spread over the
+// workgroup and the bitmap rows in its LDS (layout: lgs_block_words).  The
+// out-list offsets of L are staged too, so the row build reads only col.
+// Every thread returns its partial count.
+template <bool CE>
+__device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
+                                     const int32_t* __restrict__ col, int k, int32_t u,
+                                     int32_t d, int32_t part, int32_t parts, bool ordered,
+                                     int32_t* lds, int32_t* tmp, ElemCounter& ec) {
+  constexpr int NT = kBlockWaves * 64;
+  const int tid = threadIdx.x;
+  const int32_t W = (d + 63) >> 6;
+  int32_t* L = lds;
+  int32_t* P = lds + d;
+  int64_t* S = (int64_t*)(lds + lgs_block_s_offset(d));
+  unsigned long long* R = (unsigned long long*)(lds + lgs_block_r_offset(d));
+  const int32_t* Nu = col + rp[u];
+  for (int32_t i = tid; i < d * W; i += NT) R[i] = 0ull;
+  int32_t dd = 0;
+  if (tid < d) {
+    const int32_t v = Nu[tid];
+    const int64_t s0 = rp[v];
+    L[tid] = v;
+    S[tid] = s0;
+    dd = (int32_t)(rp[v + 1] - s0);
+  }
+  int32_t total = 0;
+  const int32_t inc = block_incl_scan(dd, tmp, total);
+  if (tid < d) P[tid + 1] = inc;
+  if (tid == 0) P[0] = 0;
+  __syncthreads();
+  if (CE && tid < 64) {
+    ec.elems += (uint64_t)d * (uint64_t)d + (uint64_t)total;
+    ec.fetches += (uint64_t)d + 1;
+  }
+  // rows: N+(L[i]) ∩ N+(u), one element of N+(L[i]) per thread
+  for (int32_t t = tid; t < total; t += NT) {
+    const int32_t i = upper_bound(P + 1, d, t);
+    const int32_t x = col[S[i] + (t - P[i])];
+    // ordered out-lists: x > L[i], so x can only sit after position i
+    const int32_t lo = ordered ? i + 1 : 0;
+    const int32_t j = lo + lower_bound(L + lo, d - lo, x);
+    if (j < d && L[j] == x) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
+  }
+  __syncthreads();
+  uint64_t c = 0;
+  if (k == 3) {
+    if (part == 0)
+      for (int32_t i = tid; i < d * W; i += NT) c += (uint64_t)__popcll(R[i]);
+    if (CE && part == 0 && tid == 0) ec.words += (uint64_t)d * W;
+    return c;
+  }
+  // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
+  int32_t pc = 0;
+  if (tid < d)
+    for (int32_t w = 0; w < W; ++w) pc += __popcll(R[(size_t)tid * W + w]);
+  int32_t pairs = 0;
+  const int32_t inc2 = block_incl_scan(pc, tmp, pairs);
+  if (tid < d) P[tid + 1] = inc2;
+  __syncthreads();
+  const int32_t p0 = (int32_t)((int64_t)pairs * part / parts);
+  const int32_t p1 = (int32_t)((int64_t)pairs * (part + 1) / parts);
+  if (k == 4) {
+    for (int32_t t = p0 + tid; t < p1; t += NT) {
+      const int32_t i = upper_bound(P + 1, d, t);
+      int32_t r = t - P[i];
+      const unsigned long long* Ri = R + (size_t)i * W;
+      int32_t w = 0;
+      for (;; ++w) {
+        const int32_t q = __popcll(Ri[w]);
+        if (r < q) break;
+        r -= q;
+      }
+      const int32_t j = w * 64 + select64(Ri[w], r);
+      const unsigned long long* Rj = R + (size_t)j * W;
+      const int32_t x0 = ordered ? ((j + 1) >> 6) : 0;
+      uint32_t cp = 0;
+      for (int32_t x = x0; x < W; ++x) cp += (uint32_t)__popcll(Ri[x] & Rj[x]);
+      c += cp;
+      if (CE) ec.words += (uint64_t)(W - x0);
+    }
+    return c;
+  }
+  if (!CE && ordered) {
+    switch (W) {
+#define GPM_LGSB5(WC) \
+  case WC:            \
+    return lgs_pairs5<false, WC, true>(P, R, d, p0, p1, tid, NT, ec);
+      GPM_LGSB5(1) GPM_LGSB5(2) GPM_LGSB5(3) GPM_LGSB5(4) GPM_LGSB5(5) GPM_LGSB5(6)
+      GPM_LGSB5(7) GPM_LGSB5(8) GPM_LGSB5(9) GPM_LGSB5(10) GPM_LGSB5(11) GPM_LGSB5(12)
+      GPM_LGSB5(13) GPM_LGSB5(14) GPM_LGSB5(15) GPM_LGSB5(16)
+#undef GPM_LGSB5
+      default: break;
+    }
+  }
+  // instrumented or unordered: words recomputed
+  for (int32_t t = p0 + tid; t < p1; t += NT) {
+    const int32_t i = upper_bound(P + 1, d, t);
+    int32_t r = t - P[i];
+    const unsigned long long* Ri = R + (size_t)i * W;
+    int32_t w = 0;
+    for (;; ++w) {
+      const int32_t q = __popcll(Ri[w]);
+      if (r < q) break;
+      r -= q;
+    }
+    const int32_t j = w * 64 + select64(Ri[w], r);
+    const unsigned long long* Rj = R + (size_t)j * W;
+    const int32_t jw = ordered ? ((j + 1) >> 6) : 0;
+    if (CE) ec.words += (uint64_t)(W - jw);
+    for (int32_t x = jw; x < W; ++x) {
+      uint64_t m = Ri[x] & Rj[x];
+      while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1ull;
+        const unsigned long long* Rl = R + (size_t)(x * 64 + b) * W;
         const int32_t y0 = ordered ? x : 0;
         for (int32_t y = y0; y < W; ++y) c += (uint64_t)__popcll(Ri[y] & Rj[y] & Rl[y]);
         if (CE) ec.words += (uint64_t)(W - y0);
@@ -1070,6 +1218,66 @@ gpm_persistent(KernelArgs a) {
   }
 }
 
+// Persistent workgroup kernel of the large-root local graphs: wave 0 pops a
+// chunk of root tasks from the per-XCD queues and shares it through LDS; the
+// whole workgroup then searches each root of the chunk in turn.
+template <bool CE>
+__global__ void __launch_bounds__(kBlockWaves * 64)
+gpm_lgs_block(KernelArgs a) {
+  extern __shared__ __attribute__((aligned(16))) int32_t blk_lds[];
+  __shared__ int32_t scan_tmp[kBlockWaves];
+  __shared__ long long chunk_lds;
+  const int home = (int)(blockIdx.x & (kQueues - 1));
+  uint32_t dead = 0;
+  int cur = -1;
+  int cur_slot = 0;
+  uint64_t acc[1] = {0};
+  ElemCounter ec;
+  for (;;) {
+    if (threadIdx.x < 64) {
+      const int64_t c = pop_chunk(a.queue_cnt, a.queue_begin, home, dead);
+      if (lane_id() == 0) chunk_lds = c;
+    }
+    __syncthreads();
+    const int64_t c = uni64(chunk_lds);
+    __syncthreads();  // read by every wave before wave 0 pops again
+    if (c < 0) break;
+    const int j = uni(find_job(a.job_chunk_begin, a.n_jobs, c));
+    if (j != cur) {
+      if (cur >= 0) flush(a.results, cur_slot, acc, 1);
+      cur = j;
+    }
+    const Job& J = a.jobs[j];
+    cur_slot = J.slot;
+    const int64_t t0 = (c - a.job_chunk_begin[j]) * (int64_t)J.chunk;
+    const int64_t t1 = min(t0 + (int64_t)J.chunk, J.n_tasks);
+    for (int64_t t = t0; t < t1; ++t) {
+      const int32_t u = uni(J.task_src[t]);
+      const int32_t d = uni((int32_t)(J.rp[u + 1] - J.rp[u]));
+      int32_t part = 0, parts = 1;
+      if (J.task_dst) {
+        const int32_t enc = uni(J.task_dst[t]);
+        part = enc & 0xffff;
+        parts = enc >> 16;
+      }
+      acc[0] += clique_lgs_block<CE>(J.rp, J.col, J.k, u, d, part, parts, J.ordered != 0,
+                                     blk_lds, scan_tmp, ec);
+      __syncthreads();  // the next root reuses the local graph's LDS
+    }
+  }
+  if (cur >= 0) flush(a.results, cur_slot, acc, 1);
+  if (CE) {
+    uint64_t e = wave_sum_u64(ec.elems);
+    uint64_t f = wave_sum_u64(ec.fetches);
+    uint64_t wo = wave_sum_u64(ec.words);
+    if (lane_id() == 0) {
+      atomicAdd(&a.counters[0], (unsigned long long)e / 64ull);
+      atomicAdd(&a.counters[1], (unsigned long long)f / 64ull);
+      atomicAdd(&a.counters[3], (unsigned long long)wo);
+    }
+  }
+}
+
 __global__ void fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -1108,6 +1316,25 @@ int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a, int
   hipError_t e = count_elems ? launch_kinds<true>(kinds, a, blocks, lds_bytes, s)
                              : launch_kinds<false>(kinds, a, blocks, lds_bytes, s);
   return (int)e;
+}
+
+int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max_blocks,
+                     size_t lds_bytes, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const void* f = count_elems ? (const void*)gpm_lgs_block<true> : (const void*)gpm_lgs_block<false>;
+  // room beyond the default dynamic LDS limit
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return (int)e;
+  // as many workgroups as can be resident at once (registers and LDS)
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlockWaves * 64, lds_bytes);
+  if (e != hipSuccess) return (int)e;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), max_blocks));
+  if (count_elems)
+    hipLaunchKernelGGL(gpm_lgs_block<true>, dim3((unsigned)blocks), dim3(kBlockWaves * 64), lds_bytes, s, a);
+  else
+    hipLaunchKernelGGL(gpm_lgs_block<false>, dim3((unsigned)blocks), dim3(kBlockWaves * 64), lds_bytes, s, a);
+  return (int)hipGetLastError();
 }
 
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream) {

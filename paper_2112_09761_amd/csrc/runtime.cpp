@@ -64,7 +64,8 @@ struct Graph {
   int64_t lgs_max_used = -1;        // root size limit the lists were built for
   // split local-graph tasks per clique size: (root, part | parts << 16)
   struct SplitTasks { int32_t* src = nullptr; int32_t* dst = nullptr; int64_t n = 0; int64_t key = -1; };
-  SplitTasks lgs_split[kMaxK + 1];
+  // [0]: per-wave roots in LDS, [1]: workgroup roots, [2]: per-wave roots in HBM
+  SplitTasks lgs_split[3][kMaxK + 1];
   // relabelled copy for non-clique plans: ids by ascending (degree, id), so
   // a symmetry bound v_j < v_i also bounds degree (lazy)
   HostCSR ren_host;
@@ -139,8 +140,10 @@ struct gpm_ctx {
   int64_t opt_clique_lds = 1, opt_rename = 1, opt_count_elements = 0, opt_autotune = 0;
   int64_t opt_lds_tile = 0, opt_max_batch = 4096, opt_serve_slots = kMaxSlots;
   int64_t opt_max_pending = 1 << 20;
-  int64_t opt_clique_algo = 0, opt_lgs_tile = 256, opt_lgs_max = kLgsMaxVertices;
+  int64_t opt_clique_algo = 0, opt_lgs_tile = 128, opt_lgs_max = kLgsMaxVertices;
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
+  int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
+  int lds_block_max = 65536;                    // dynamic LDS per workgroup (bytes)
   int64_t opt_tune_min_ms = 20;
   int64_t opt_wedge_mem = int64_t(16) << 30;   // cap of the 4-cycle counter arrays
   // autotuner cache: (graph, pattern, mode) -> tuned knob values
@@ -207,11 +210,12 @@ static void free_graph(Graph& g) {
   dev_free(g.big_src);
   dev_free(g.big_dst);
   g.lgs_vtx = g.big_src = g.big_dst = nullptr;
-  for (auto& t : g.lgs_split) {
-    dev_free(t.src);
-    dev_free(t.dst);
-    t = Graph::SplitTasks{};
-  }
+  for (auto& row : g.lgs_split)
+    for (auto& t : row) {
+      dev_free(t.src);
+      dev_free(t.dst);
+      t = Graph::SplitTasks{};
+    }
   dev_free(g.lo_src);
   dev_free(g.lo_dst);
   g.lo_src = g.lo_dst = nullptr;
@@ -296,22 +300,37 @@ static gpm_status ensure_lgs(gpm_ctx* c, Graph& g, int64_t lgs_max) {
   if (st) return st;
   const HostCSR& d = g.dag_host;
   std::vector<int32_t> order;
-  for (int64_t u = 0; u < d.n; ++u)
-    if (d.rp[u + 1] - d.rp[u] >= 2) order.push_back((int32_t)u);
+  std::vector<char> too_long(d.n, 0);
+  for (int64_t u = 0; u < d.n; ++u) {
+    if (d.rp[u + 1] - d.rp[u] < 2) continue;
+    // the kernels index a root's row-build work (the summed out-degrees of its
+    // out-neighbours) with int32; larger roots take the edge kernel
+    int64_t work = 0;
+    for (int64_t p = d.rp[u]; p < d.rp[u + 1]; ++p) work += d.rp[d.col[p] + 1] - d.rp[d.col[p]];
+    if (work > (int64_t)INT32_MAX) {
+      too_long[u] = 1;
+      continue;
+    }
+    order.push_back((int32_t)u);
+  }
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return d.rp[a + 1] - d.rp[a] > d.rp[b + 1] - d.rp[b];
   });
   g.lgs_deg.resize(order.size());
   std::vector<int32_t> bs, bd;
+  auto add_big = [&](int64_t u) {
+    for (int64_t p = d.rp[u]; p < d.rp[u + 1]; ++p) {
+      bs.push_back((int32_t)u);
+      bd.push_back(d.col[p]);
+    }
+  };
   for (size_t i = 0; i < order.size(); ++i) {
     int64_t u = order[i];
     g.lgs_deg[i] = d.rp[u + 1] - d.rp[u];
-    if (g.lgs_deg[i] > lgs_max)
-      for (int64_t p = d.rp[u]; p < d.rp[u + 1]; ++p) {
-        bs.push_back((int32_t)u);
-        bd.push_back(d.col[p]);
-      }
+    if (g.lgs_deg[i] > lgs_max) add_big(u);
   }
+  for (int64_t u = 0; u < d.n; ++u)
+    if (too_long[u]) add_big(u);
   st = dev_upload(c, &g.lgs_vtx, order.data(), order.size());
   if (st) return st;
   g.n_big = (int64_t)bs.size();
@@ -351,10 +370,10 @@ static gpm_status ensure_lower(gpm_ctx* c, Graph& g) {
 // Split the local-graph roots [lo, hi) of the heaviest-first order into
 // sub-tasks: a root's cost grows like d^(k-2) (local edges for k = 4, local
 // triangles for k = 5); a root gets ceil(cost / share) parts, share being a
-// quarter of an even split over `waves` waves.
-static gpm_status ensure_lgs_split(gpm_ctx* c, Graph& g, int k, int64_t lo, int64_t hi,
-                                   int64_t waves, Graph::SplitTasks** out) {
-  Graph::SplitTasks& T = g.lgs_split[k];
+// quarter of an even split over `waves` execution units (waves or workgroups).
+static gpm_status ensure_lgs_split(gpm_ctx* c, Graph& g, int which, int k, int64_t lo,
+                                   int64_t hi, int64_t waves, Graph::SplitTasks** out) {
+  Graph::SplitTasks& T = g.lgs_split[which][k];
   const int64_t key = (lo << 40) ^ (hi << 8) ^ waves ^ (g.lgs_max_used << 50);
   if (T.key == key) { *out = &T; return GPM_OK; }
   dev_free(T.src);
@@ -527,6 +546,14 @@ static int default_chunk(const gpm_ctx* c, int kind) {
 
 static int64_t kWedgeWaves(const gpm_ctx* c) { return (int64_t)c->cus * 8; }
 
+// Largest local graph of the workgroup kernel: one vertex per thread in its
+// scans, and its tile (plus the kernel's static LDS) within the workgroup's LDS.
+static int64_t lgs_block_max_vertices(const gpm_ctx* c) {
+  int64_t d = kLgsBlockMaxVertices;
+  while (d > 0 && lgs_block_words(d) * 4 + 256 > (int64_t)c->lds_block_max) --d;
+  return d;
+}
+
 static int lds_tile(const gpm_ctx* c) {
   return c->opt_lds_tile > 0 ? (int)c->opt_lds_tile : 512;
 }
@@ -573,25 +600,50 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
                                     [](int64_t x, int64_t y) { return x > y; }) - dg.begin();
       int64_t hi = std::upper_bound(dg.begin(), dg.end(), (int64_t)(p.k - 1),
                                     [](int64_t x, int64_t y) { return x > y; }) - dg.begin();
-      Job L = J;
-      L.kind = kJobCliqueLgs;
-      L.vertex_tasks = 1;
-      L.task_src = g.lgs_vtx + lo;
-      L.task_dst = nullptr;
-      L.n_tasks = std::max<int64_t>(hi - lo, 0);
-      L.chunk = c->opt_chunk > 0 ? (int)c->opt_chunk : 1;
-      if (p.k >= 5 && c->opt_lgs_split && hi > lo) {
-        Graph::SplitTasks* T = nullptr;
-        st = ensure_lgs_split(c, g, p.k, lo, hi, (int64_t)c->cus * 16, &T);
-        if (st) return st;
-        L.task_src = T->src;
-        L.task_dst = T->dst;
-        L.n_tasks = T->n;
+      // [lo, hi) splits by out-degree d into [lo, b0): d above the workgroup
+      // limit (per wave, rows in HBM); [b0, mid): above the per-wave LDS tile,
+      // one workgroup per root; [mid, hi): per wave, rows in LDS
+      int64_t b0 = lo, mid = lo;
+      if (c->opt_lgs_block && hi > lo) {
+        auto first_at_most = [&](int64_t v) {
+          return std::lower_bound(dg.begin() + lo, dg.begin() + hi, v,
+                                  [](int64_t x, int64_t y) { return x > y; }) - dg.begin();
+        };
+        mid = first_at_most(c->opt_lgs_tile);
+        b0 = std::min(first_at_most(lgs_block_max_vertices(c)), mid);
       }
-      L.cap = (int32_t)std::min<int64_t>(cap, c->opt_lgs_max);
-      js.jobs.push_back(L);
-      js.need_words.push_back(0);  // sized at launch from the LDS tile
-      qw.n_jobs += 1;
+      auto add_lgs = [&](int kind, int64_t a, int64_t b, int which, int64_t units,
+                         bool split, bool always) -> gpm_status {
+        if (b <= a && !always) return GPM_OK;
+        Job L = J;
+        L.kind = kind;
+        L.vertex_tasks = 1;
+        L.task_src = g.lgs_vtx + a;
+        L.task_dst = nullptr;
+        L.n_tasks = std::max<int64_t>(b - a, 0);
+        L.chunk = c->opt_chunk > 0 ? (int)c->opt_chunk : 1;
+        if (split && c->opt_lgs_split && b > a) {
+          Graph::SplitTasks* T = nullptr;
+          gpm_status s2 = ensure_lgs_split(c, g, which, p.k, a, b, units, &T);
+          if (s2) return s2;
+          L.task_src = T->src;
+          L.task_dst = T->dst;
+          L.n_tasks = T->n;
+        }
+        // largest root of the range (heaviest first)
+        L.cap = (int32_t)(b > a ? dg[a] : std::min<int64_t>(cap, c->opt_lgs_max));
+        js.jobs.push_back(L);
+        js.need_words.push_back(0);  // sized at launch from the LDS tile
+        qw.n_jobs += 1;
+        return GPM_OK;
+      };
+      const int64_t waves = (int64_t)c->cus * 16;
+      st = add_lgs(kJobCliqueLgs, mid, hi, 0, waves, p.k >= 5, true);
+      if (st) return st;
+      st = add_lgs(kJobCliqueLgsBlock, b0, mid, 1, (int64_t)c->cus, p.k >= 4, false);
+      if (st) return st;
+      st = add_lgs(kJobCliqueLgs, lo, b0, 2, waves, p.k >= 5, false);
+      if (st) return st;
       if (g.n_big) {
         Job B = J;
         B.kind = kJobClique;
@@ -725,7 +777,7 @@ static std::vector<std::pair<std::string, std::vector<int64_t>>> tune_space(cons
                                                                              int mode) {
   const bool clique = p.n_edges == p.k * (p.k - 1) / 2;
   if (clique && p.k <= 5)
-    return {{"lgs_tile", {256, 192, 128}}, {"waves_per_cu", {16, 12, 24}}, {"chunk", {0, 2}}};
+    return {{"lgs_tile", {128, 64, 192}}, {"waves_per_cu", {16, 12, 24}}, {"chunk", {0, 2}}};
   if (clique) return {{"lds_tile", {0, 256, 128}}, {"chunk", {0, 4, 16}}, {"waves_per_cu", {16, 12}}};
   (void)mode;
   return {{"leaf_cap", {128, 0, 32, 512}}, {"chunk", {0, 2, 32}}, {"granularity", {0, 1}},
@@ -903,14 +955,18 @@ static std::vector<LaunchPlan> plan_launches(JobPlanSet& js, std::vector<int>& p
   const int nj = (int)js.jobs.size();
   perm.resize(nj);
   for (int i = 0; i < nj; ++i) perm[i] = i;
-  if (fission) std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-    return js.jobs[a].kind < js.jobs[b].kind;
+  // workgroup jobs run in a kernel of their own, even without fission
+  auto own = [&](int i) { return js.jobs[i].kind == kJobCliqueLgsBlock; };
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+    if (own(a) != own(b)) return own(a);
+    return fission && js.jobs[a].kind < js.jobs[b].kind;
   });
   std::vector<LaunchPlan> out;
   for (int i = 0; i < nj; ++i) {
     const Job& J = js.jobs[perm[i]];
     uint32_t kb = 1u << J.kind;
-    if (out.empty() || (fission && out.back().kinds != kb)) {
+    if (out.empty() || ((fission || own(perm[i]) || out.back().kinds == kKindCliqueLgsBlock) &&
+                        out.back().kinds != kb)) {
       LaunchPlan L;
       L.first = i;
       L.kinds = kb;
@@ -974,6 +1030,13 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
       if (jobs[i].cap > lgs_T) need[i] = std::max<int64_t>(need[i], lgs_tile_words(jobs[i].cap));
     }
   if (lgs_T) lds_words = std::max<int32_t>(lds_words, (int32_t)align_up((size_t)lgs_tile_words(lgs_T), 4));
+  // workgroup kernel: room for the largest root of its jobs
+  int64_t blk_cap = 0;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].kind == kJobCliqueLgsBlock) blk_cap = std::max<int64_t>(blk_cap, jobs[i].cap);
+  const size_t blk_lds = blk_cap ? (size_t)align_up((size_t)lgs_block_words(blk_cap), 4) * 4 : 0;
+  if (blk_cap && (blk_cap > kLgsBlockMaxVertices || blk_lds + 256 > (size_t)c->lds_block_max))
+    return fail(c, GPM_E_DEVICE, "local graph exceeds the workgroup LDS");
 
   // frontier sizing (adaptive buffering): one region of `stride` words per wave
   int64_t stride = 0;
@@ -1103,7 +1166,13 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     a.zbuf = (L.kinds & kKindCycleWedge) ? s.d_zero : nullptr;
     a.zstride = zstride;
     size_t lb = uses_lds ? lds_bytes : 0;
-    int e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
+    int e;
+    if (L.kinds == kKindCliqueLgsBlock) {
+      a.lds_words = (int32_t)(blk_lds / 4);
+      e = launch_lgs_block(c->opt_count_elements != 0, a, c->cus, L.chunks, blk_lds, s.stream);
+    } else {
+      e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
+    }
     if (e) return fail(c, GPM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
     ++n_launch;
   }
@@ -1415,6 +1484,12 @@ gpm_status gpm_create(gpm_ctx** out, int device, void* hip_stream, size_t hbm_bu
   c->device = device;
   c->user_stream = (hipStream_t)hip_stream;
   c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+            hipSuccess && lds > 0)
+      c->lds_block_max = lds;
+  }
   size_t freeb = 0, total = 0;
   if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
     delete c;
@@ -1453,9 +1528,10 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "count_elements") c->opt_count_elements = v != 0;
   else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
+  else if (k == "lgs_block") c->opt_lgs_block = v != 0;
   else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
-  else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..1024"); c->opt_lgs_max = v; }
+  else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..2048"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;
   else if (k == "wedge_mem") { if (v < (1 << 20)) return fail(c, GPM_E_INVAL, "wedge_mem >= 1 MiB"); c->opt_wedge_mem = v; }

@@ -162,7 +162,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
         for opt, vals in [("chunk", [1, 3, 64]), ("waves_per_cu", [1, 4, 32]),
                           ("lds_tile", [32, 64, 4096]), ("clique_lds", [0]),
                           ("granularity", [1]), ("clique_algo", [1, 2]),
-                          ("lgs_tile", [64, 128]), ("lgs_max", [64, 100]),
+                          ("lgs_tile", [64, 256]), ("lgs_max", [64, 100]),
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
                           ("rename", [0]), ("cycle4_algo", [1, 2])]:
             for v in vals:
@@ -172,7 +172,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                 assert ctx.count(gid, "cycle4", E) == exp_c4e, (opt, v)
             ctx.set_option(opt, {"chunk": 0, "waves_per_cu": 0, "lds_tile": 0,
                                  "clique_lds": 1, "granularity": 0, "clique_algo": 0,
-                                 "lgs_tile": 256, "lgs_max": 1024, "lgs_split": 1,
+                                 "lgs_tile": 128, "lgs_max": 2048, "lgs_split": 1,
                                  "leaf_cap": 128, "rename": 1, "cycle4_algo": 0}[opt])
     finally:
         ctx.unload(gid)
@@ -207,8 +207,104 @@ def test_large_roots_take_edge_kernel(ctx, oracle):
                 assert ctx.count(gid, synth_clique(k)) == oracle.cliques(g, k), (lim, k)
         assert ctx.motifs(gid, 4) == oracle.motifs4(g)
     finally:
-        ctx.set_option("lgs_max", 1024)
+        ctx.set_option("lgs_max", 2048)
         ctx.unload(gid)
+
+
+def esym(parts, k):
+    """k-cliques of the complete multipartite graph with these part sizes: the
+    elementary symmetric polynomial e_k of the sizes."""
+    e = [1] + [0] * k
+    for p in parts:
+        for j in range(k, 0, -1):
+            e[j] += e[j - 1] * p
+    return e[k]
+
+
+def test_esym_closed_form():
+    import itertools
+    import math
+    parts = [3, 1, 4, 1, 5, 2]
+    for k in range(1, 7):
+        assert esym(parts, k) == sum(math.prod(c) for c in itertools.combinations(parts, k))
+    assert esym([1] * 30, 5) == math.comb(30, 5)
+
+
+@pytest.mark.parametrize("parts,k5_both", [
+    ([1] * 65, True),                 # K_65: out-degrees 0..64
+    ([3] * 97 + [1] * 10, True),      # n = 301, ragged rows
+    ([1] * 1025, False),              # K_1025: the largest workgroup root, d = 1024
+    ([2] * 550, False),               # n = 1100: roots above the workgroup limit too
+])
+def test_workgroup_local_graphs(ctx, parts, k5_both):
+    """Roots with more out-neighbours than the per-wave tile are searched by a
+    whole workgroup (up to 1024 out-neighbours); larger ones by one wave with
+    rows in HBM.  Dense multipartite graphs put roots in all three ranges;
+    every count must equal the closed form, with the workgroup path on and off."""
+    g = synth.complete_multipartite(parts)
+    gid = ctx.load(g)
+    try:
+        ctx.set_option("lgs_tile", 64)
+        for k in (3, 4, 5):
+            for blk in ((1, 0) if (k < 5 or k5_both) else (1,)):
+                ctx.set_option("lgs_block", blk)
+                assert ctx.count(gid, synth_clique(k)) == esym(parts, k), (k, blk)
+    finally:
+        ctx.set_option("lgs_block", 1)
+        ctx.set_option("lgs_tile", 128)
+        ctx.unload(gid)
+
+
+def test_workgroup_rmat_options(ctx, oracle):
+    """R-MAT graph with 245 roots above a 64-vertex tile: workgroup path with
+    and without splitting, instrumented kernels, and a batch that mixes the
+    workgroup kernel with the per-wave kernel, all equal to the oracle."""
+    from paper_2112_09761_amd import gpm
+    g = synth.rmat(13, 16, seed=1301)
+    gid = ctx.load(g)
+    exp = {k: oracle.cliques(g, k) for k in (3, 4, 5)}
+    try:
+        ctx.set_option("lgs_tile", 64)
+        for opt, v in [("lgs_split", 0), ("lgs_split", 1), ("count_elements", 1),
+                       ("count_elements", 0), ("lgs_block", 0), ("lgs_block", 1)]:
+            ctx.set_option(opt, v)
+            for k in (3, 4, 5):
+                assert ctx.count(gid, synth_clique(k)) == exp[k], (opt, v, k)
+        qs = [gpm.count_query(gid, synth_clique(5), V), gpm.motif_query(gid, 4),
+              gpm.count_query(gid, "clique4", V), gpm.count_query(gid, "diamond", E)]
+        res = ctx.count_batch(qs)
+        assert res[0] == exp[5] and res[2] == exp[4]
+        assert res[1] == oracle.motifs4(g)
+        assert res[3] == oracle.count(g, "diamond", False)
+    finally:
+        ctx.set_option("lgs_tile", 128)
+        ctx.set_option("lgs_split", 1)
+        ctx.set_option("count_elements", 0)
+        ctx.set_option("lgs_block", 1)
+        ctx.unload(gid)
+
+
+def test_workgroup_unordered_dag(ctx):
+    """A DAG given by the caller whose orientation does not follow vertex ids
+    (u -> v iff pi(u) < pi(v) for a random permutation pi): the workgroup
+    path takes its unordered branches."""
+    from paper_2112_09761_amd import gpm
+    parts = [3] * 97 + [1] * 10
+    g = synth.complete_multipartite(parts)
+    rng = np.random.default_rng(1302)
+    pi = rng.permutation(g.n)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    keep = pi[src] < pi[g.col]
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src[keep], minlength=g.n), out=rp[1:])
+    did = ctx.load_csr(rp, g.col[keep], gpm.GPM_CSR_DAG | gpm.GPM_VALIDATE)
+    try:
+        ctx.set_option("lgs_tile", 64)
+        for k in (3, 4, 5):
+            assert ctx.count(did, synth_clique(k)) == esym(parts, k), k
+    finally:
+        ctx.set_option("lgs_tile", 128)
+        ctx.unload(did)
 
 
 def test_edge_cases(ctx):
