@@ -83,6 +83,8 @@ typedef struct {
 } gpm_graph_meta;
 
 /* Statistics of the last gpm_count / gpm_motifs / gpm_count_batch call. */
+#define GPM_MAX_LAUNCH_STATS 8
+
 typedef struct {
     double kernel_ms;        /* sum of the call's kernel times (HIP events)  */
     double total_ms;         /* host wall time of the call                   */
@@ -98,6 +100,21 @@ typedef struct {
     int64_t frontier_bytes;  /* device frontier buffer size                  */
     int32_t launches;        /* kernel launches of the call                   */
     int32_t variant;         /* kernel variant the autotuner chose            */
+    /* per launch, in launch order (the first GPM_MAX_LAUNCH_STATS launches) */
+    int32_t n_launch_stats;  /* entries filled in the arrays below           */
+    int32_t reserved;
+    uint32_t launch_kinds[GPM_MAX_LAUNCH_STATS];  /* job kinds of the launch as
+                                a bit mask: 1<<1 clique edge kernel, 1<<2 DFS
+                                plan, 1<<3 per-edge motif terms, 1<<4
+                                per-vertex motif terms, 1<<5 local-graph
+                                cliques (one wave per root), 1<<6 4-cycle
+                                wedges, 1<<7 local-graph cliques (one
+                                workgroup per root; its own kernel)          */
+    double launch_ms[GPM_MAX_LAUNCH_STATS];        /* duration (HIP events)   */
+    int64_t launch_elements[GPM_MAX_LAUNCH_STATS]; /* as the totals above, per */
+    int64_t launch_fetches[GPM_MAX_LAUNCH_STATS];  /* launch (-1 unless       */
+    int64_t launch_written[GPM_MAX_LAUNCH_STATS];  /* "count_elements" is 1)  */
+    int64_t launch_words[GPM_MAX_LAUNCH_STATS];
 } gpm_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -124,7 +141,8 @@ const char *gpm_last_error(const gpm_ctx *ctx);
 /* Set a tuning option (for tests and the autotuner's search space):
  *   "granularity"     0 auto, 1 vertex tasks, 2 edge tasks
  *   "chunk"           tasks per queue pop (0 = auto)
- *   "waves_per_cu"    persistent waves per compute unit (0 = auto)
+ *   "waves_per_cu"    persistent waves per compute unit (0 = auto: 24 for
+ *                     local-graph clique launches, 16 otherwise)
  *   "setop"           0 auto, 1 binary search, 2 merge path
  *   "clique_lds"      1 = clique kernel keeps frontiers in LDS (default),
  *                     0 = force the generic kernel with HBM frontiers

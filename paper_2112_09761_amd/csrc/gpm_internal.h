@@ -110,21 +110,24 @@ struct KernelArgs {
   int64_t zstride;                 // words of zbuf per wave
 };
 
-// Local-graph tile of T vertices: L[T] | P[T + 1] | R[T * ceil(T / 64)] uint64,
-// sizes in int32 words (R starts 8-byte aligned).
-__host__ __device__ inline int64_t lgs_rows_offset(int64_t T) { return (2 * T + 2) & ~int64_t(1); }
+// Local-graph tile of T vertices, in int32 words: L[T] | P[T + 1] | (pad to
+// 8 B) | H[lgs_hash_slots(T)] uint64 (hash of L: vertex -> position) |
+// R[T * ceil(T / 64)] uint64 (bitmap rows).  A root of d <= T vertices uses
+// the first lgs_hash_slots(d) slots of H.
+__host__ __device__ inline int64_t lgs_hash_slots(int64_t d) {
+  int64_t s = 2;
+  while (s < 2 * d) s <<= 1;  // load factor <= 1/2: every probe sequence meets an empty slot
+  return s;
+}
+__host__ __device__ inline int64_t lgs_hash_offset(int64_t T) { return (2 * T + 2) & ~int64_t(1); }
+__host__ __device__ inline int64_t lgs_rows_offset(int64_t T) {
+  return lgs_hash_offset(T) + 2 * lgs_hash_slots(T);
+}
 __host__ __device__ inline int64_t lgs_tile_words(int64_t T) {
   return lgs_rows_offset(T) + 2 * T * ((T + 63) / 64);
 }
 
-// Workgroup local graph of d vertices, in int32 words: L[d] | P[d + 1] |
-// (pad to 8 B) | S[d] int64 (offsets of the out-lists of L) | R[d * ceil(d / 64)]
-// uint64.  Sized per root; the launch provides room for its largest root.
-__host__ __device__ inline int64_t lgs_block_s_offset(int64_t d) { return (2 * d + 2) & ~int64_t(1); }
-__host__ __device__ inline int64_t lgs_block_r_offset(int64_t d) { return lgs_block_s_offset(d) + 2 * d; }
-__host__ __device__ inline int64_t lgs_block_words(int64_t d) {
-  return lgs_block_r_offset(d) + 2 * d * ((d + 63) / 64);
-}
+// The workgroup kernel lays out a root of d vertices as a tile with T = d.
 
 // Host-side launchers (kernels.hip).  Return a hipError_t as int.
 int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a,

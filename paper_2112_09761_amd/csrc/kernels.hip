@@ -286,6 +286,90 @@ __device__ __forceinline__ int select64(uint64_t x, int r) {
   return pos;
 }
 
+// Hash of a local graph's vertex list L (open addressing, linear probing):
+// slot = (position << 32) | (vertex + 1), 0 = empty.  lgs_hash_slots(d)
+// slots for d vertices keep the load factor at most 1/2.
+__device__ __forceinline__ int32_t lgs_hash_bits(int32_t d) {
+  return 32 - __clz(2 * d - 1);  // 2^bits = lgs_hash_slots(d) >= 2d
+}
+
+__device__ __forceinline__ uint32_t lgs_hash(int32_t x, int32_t bits) {
+  return ((uint32_t)x * 0x9E3779B1u) >> (32 - bits);  // Fibonacci hashing
+}
+
+template <typename TH>
+__device__ __forceinline__ void lgs_hash_put(TH* H, int32_t bits, int32_t x, int32_t pos) {
+  const uint32_t mask = (1u << bits) - 1u;
+  const unsigned long long e = ((unsigned long long)(uint32_t)pos << 32) | ((uint32_t)x + 1u);
+  for (uint32_t s = lgs_hash(x, bits);; s = (s + 1u) & mask)
+    if (atomicCAS(&H[s], 0ull, e) == 0ull) return;
+}
+
+// Position of x in L, or -1.
+template <typename TH>
+__device__ __forceinline__ int32_t lgs_hash_get(const TH* H, int32_t bits, int32_t x) {
+  const uint32_t mask = (1u << bits) - 1u;
+  for (uint32_t s = lgs_hash(x, bits);; s = (s + 1u) & mask) {
+    const unsigned long long e = H[s];
+    if (e == 0ull) return -1;
+    if ((uint32_t)e == (uint32_t)x + 1u) return (int32_t)(e >> 32);
+  }
+}
+
+// Rows of a local graph: R_i = positions in L of N+(L[i]) ∩ L, for rows
+// i = first, first + step, ... (the calling wave owns these rows; its lanes
+// walk the row's out-list 64 elements at a time and look each element up in
+// the hash H of L).  Out-lists are sorted, so a row stops at the first batch
+// whose elements all exceed max(L).  With BITS the hits are set in R (rows
+// of W words); the number of hits is returned either way (per lane).
+template <bool CE, bool BITS, typename TL, typename TH, typename TR>
+__device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const TL* L,
+                                                   int32_t d, int32_t W, const TH* H,
+                                                   int32_t bits, TR* R, int32_t first,
+                                                   int32_t step, ElemCounter& ec) {
+  constexpr int U = 4;  // batches of 64 elements whose loads are in flight together
+  const int l = lane_id();
+  const int32_t lmax = uni(L[d - 1]);
+  uint64_t hits = 0;
+  int64_t nb = 0, ne = 0;  // bounds of the next row, loaded one row ahead
+  if (first < d) {
+    const int32_t v = uni(L[first]);
+    nb = uni64(rp[v]);
+    ne = uni64(rp[v + 1]);
+  }
+  for (int32_t i = first; i < d; i += step) {
+    const int64_t b = nb, e = ne;
+    if (i + step < d) {
+      const int32_t v = uni(L[i + step]);
+      nb = uni64(rp[v]);
+      ne = uni64(rp[v + 1]);
+    }
+    if (CE) ec.elems += (uint64_t)(e - b);
+    for (int64_t pb = b; pb < e; pb += 64 * U) {
+      int32_t x[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int64_t p = pb + q * 64 + l;
+        x[q] = p < e ? col[p] : INT_MAX;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (x[q] <= lmax) {
+          const int32_t j = lgs_hash_get(H, bits, x[q]);
+          if (j >= 0) {
+            ++hits;
+            if (BITS) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
+          }
+        }
+      }
+      // out-lists are sorted: once every element exceeds max(L), none further can hit
+      if (wave_ballot(x[U - 1] <= lmax) == 0ull) break;
+    }
+  }
+  return hits;
+}
+
 // L: d ints, P: d + 1 ints, R: d * W uint64 (W = ceil(d / 64)).
 // Sub-task `part` of `parts` handles its share of the local edges (i, j), so
 // the heaviest roots are spread over several waves (each rebuilds the local
@@ -353,57 +437,34 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
   return c;
 }
 
-template <bool CE, typename TL, typename TP, typename TR>
+template <bool CE, typename TL, typename TP, typename TH, typename TR>
 __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
                                                int32_t u, int32_t d, int32_t part,
                                                int32_t parts, bool ordered, TL* L, TP* P,
-                                               TR* R, ElemCounter& ec) {
+                                               TH* H, TR* R, ElemCounter& ec) {
   const int l = lane_id();
   const int32_t W = (d + 63) >> 6;
+  const int32_t bits = lgs_hash_bits(d);
   const int32_t* Nu = col + rp[u];
   for (int32_t i = l; i < d; i += 64) L[i] = Nu[i];
-  for (int32_t i = l; i < d * W; i += 64) R[i] = 0ull;
-  // P[i] = sum of out-degrees of L[0..i)
-  int32_t running = 0;
-  for (int32_t ib = 0; ib < d; ib += 64) {
-    int32_t i = ib + l;
-    int32_t dd = 0;
-    if (i < d) {
-      int32_t v = Nu[i];
-      dd = (int32_t)(rp[v + 1] - rp[v]);
-    }
-    int32_t inc = wave_incl_scan(dd);
-    if (i < d) P[i + 1] = running + inc;
-    running += __shfl(inc, 63, 64);
-  }
-  if (l == 0) P[0] = 0;
+  for (int32_t i = l; i < (1 << bits); i += 64) H[i] = 0ull;
+  if (k > 3)
+    for (int32_t i = l; i < d * W; i += 64) R[i] = 0ull;
   wave_sync_mem();
-  const int32_t total = uni(running);
+  for (int32_t i = l; i < d; i += 64) lgs_hash_put(H, bits, Nu[i], i);
+  wave_sync_mem();
   if (CE) {
-    ec.elems += (uint64_t)d * (uint64_t)d + (uint64_t)total;
+    ec.elems += (uint64_t)d * (uint64_t)d;
     ec.fetches += (uint64_t)d + 1;
   }
-  // rows: N+(L[i]) ∩ N+(u), one element of N+(L[i]) per lane, membership by
-  // binary search in the staged list
-  for (int32_t tb = 0; tb < total; tb += 64) {
-    int32_t t = tb + l;
-    if (t < total) {
-      int32_t i = upper_bound(P + 1, d, t);
-      int32_t v = L[i];
-      int32_t x = col[rp[v] + (t - P[i])];
-      int32_t j = lower_bound(L, d, x);
-      if (j < d && L[j] == x) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
-    }
-  }
+  // k = 3: every hit is a triangle at this root
+  if (k == 3)
+    return part == 0 ? lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec) : 0;
+  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
   wave_sync_mem();
   uint64_t c = 0;
-  if (k == 3) {
-    if (part == 0)
-      for (int32_t i = l; i < d * W; i += 64) c += (uint64_t)__popcll(R[i]);
-    if (CE && part == 0 && l == 0) ec.words += (uint64_t)d * W;
-    return c;
-  }
+  int32_t running;
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
   running = 0;
   for (int32_t ib = 0; ib < d; ib += 64) {
@@ -452,12 +513,10 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
 #define GPM_LGS5(WC) \
   case WC:           \
     return c + lgs_pairs5<CE, WC, true>(P, R, d, p0, p1, l, 64, ec);
-      GPM_LGS5(1) GPM_LGS5(2) GPM_LGS5(3) GPM_LGS5(4) GPM_LGS5(5) GPM_LGS5(6) GPM_LGS5(7)
-      GPM_LGS5(8) GPM_LGS5(9) GPM_LGS5(10) GPM_LGS5(11) GPM_LGS5(12) GPM_LGS5(13)
-      GPM_LGS5(14) GPM_LGS5(15) GPM_LGS5(16) GPM_LGS5(17) GPM_LGS5(18) GPM_LGS5(19)
-      GPM_LGS5(20) GPM_LGS5(21) GPM_LGS5(22) GPM_LGS5(23) GPM_LGS5(24) GPM_LGS5(25)
-      GPM_LGS5(26) GPM_LGS5(27) GPM_LGS5(28) GPM_LGS5(29) GPM_LGS5(30) GPM_LGS5(31)
-      GPM_LGS5(32)
+      // per-wave tiles hold at most 256 vertices (4 words per row); wider
+      // rows (roots in HBM) take the generic loop, which keeps the
+      // kernel's register count, and so its occupancy, low
+      GPM_LGS5(1) GPM_LGS5(2) GPM_LGS5(3) GPM_LGS5(4)
 #undef GPM_LGS5
       default: break;
     }
@@ -520,9 +579,8 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* tmp, int3
 
 // The same local-graph search as clique_lgs, for a root u with
 // d <= kLgsBlockMaxVertices out-neighbours, with every step spread over the
-// workgroup and the bitmap rows in its LDS (layout: lgs_block_words).  The
-// out-list offsets of L are staged too, so the row build reads only col.
-// Every thread returns its partial count.
+// workgroup (rows dealt round-robin to its waves) and the tile (T = d) in
+// its LDS.  Every thread returns its partial count.
 template <bool CE>
 __device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
                                      const int32_t* __restrict__ col, int k, int32_t u,
@@ -530,47 +588,36 @@ __device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
                                      int32_t* lds, int32_t* tmp, ElemCounter& ec) {
   constexpr int NT = kBlockWaves * 64;
   const int tid = threadIdx.x;
+  const int wv = tid >> 6;
   const int32_t W = (d + 63) >> 6;
+  const int32_t bits = lgs_hash_bits(d);
   int32_t* L = lds;
   int32_t* P = lds + d;
-  int64_t* S = (int64_t*)(lds + lgs_block_s_offset(d));
-  unsigned long long* R = (unsigned long long*)(lds + lgs_block_r_offset(d));
+  unsigned long long* H = (unsigned long long*)(lds + lgs_hash_offset(d));
+  unsigned long long* R = (unsigned long long*)(lds + lgs_rows_offset(d));
   const int32_t* Nu = col + rp[u];
-  for (int32_t i = tid; i < d * W; i += NT) R[i] = 0ull;
-  int32_t dd = 0;
+  for (int32_t i = tid; i < (1 << bits); i += NT) H[i] = 0ull;
+  if (k > 3)
+    for (int32_t i = tid; i < d * W; i += NT) R[i] = 0ull;
+  int32_t v = 0;
   if (tid < d) {
-    const int32_t v = Nu[tid];
-    const int64_t s0 = rp[v];
+    v = Nu[tid];
     L[tid] = v;
-    S[tid] = s0;
-    dd = (int32_t)(rp[v + 1] - s0);
   }
-  int32_t total = 0;
-  const int32_t inc = block_incl_scan(dd, tmp, total);
-  if (tid < d) P[tid + 1] = inc;
-  if (tid == 0) P[0] = 0;
+  __syncthreads();
+  if (tid < d) lgs_hash_put(H, bits, v, tid);
   __syncthreads();
   if (CE && tid < 64) {
-    ec.elems += (uint64_t)d * (uint64_t)d + (uint64_t)total;
+    ec.elems += (uint64_t)d * (uint64_t)d;
     ec.fetches += (uint64_t)d + 1;
   }
-  // rows: N+(L[i]) ∩ N+(u), one element of N+(L[i]) per thread
-  for (int32_t t = tid; t < total; t += NT) {
-    const int32_t i = upper_bound(P + 1, d, t);
-    const int32_t x = col[S[i] + (t - P[i])];
-    // ordered out-lists: x > L[i], so x can only sit after position i
-    const int32_t lo = ordered ? i + 1 : 0;
-    const int32_t j = lo + lower_bound(L + lo, d - lo, x);
-    if (j < d && L[j] == x) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
-  }
+  // k = 3: every hit is a triangle at this root
+  if (k == 3)
+    return part == 0 ? lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec)
+                     : 0;
+  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec);
   __syncthreads();
   uint64_t c = 0;
-  if (k == 3) {
-    if (part == 0)
-      for (int32_t i = tid; i < d * W; i += NT) c += (uint64_t)__popcll(R[i]);
-    if (CE && part == 0 && tid == 0) ec.words += (uint64_t)d * W;
-    return c;
-  }
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
   int32_t pc = 0;
   if (tid < d)
@@ -578,6 +625,7 @@ __device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
   int32_t pairs = 0;
   const int32_t inc2 = block_incl_scan(pc, tmp, pairs);
   if (tid < d) P[tid + 1] = inc2;
+  if (tid == 0) P[0] = 0;
   __syncthreads();
   const int32_t p0 = (int32_t)((int64_t)pairs * part / parts);
   const int32_t p1 = (int32_t)((int64_t)pairs * (part + 1) / parts);
@@ -1104,18 +1152,20 @@ gpm_persistent(KernelArgs a) {
           part = enc & 0xffff;
           parts = enc >> 16;
         }
-        // tile layout: L[T] | P[T + 1] | (pad to 8 B) | R[T * ceil(T / 64)] (uint64)
+        // tile layout (lgs_tile_words): L | P | H | R
         if (d <= a.lgs_tile) {
           int32_t* L = my;
           int32_t* Pp = L + a.lgs_tile;
+          unsigned long long* H = (unsigned long long*)(my + lgs_hash_offset(a.lgs_tile));
           unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, R,
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
                                    ec);
         } else {
           int32_t* L = fb;
           int32_t* Pp = fb + J.cap;
+          unsigned long long* H = (unsigned long long*)(fb + lgs_hash_offset(J.cap));
           unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, R,
+          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
                                    ec);
         }
       }

@@ -103,6 +103,11 @@ struct Slot {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evl[GPM_MAX_LAUNCH_STATS] = {};  // after each of the first launches
+  uint32_t lkinds[GPM_MAX_LAUNCH_STATS] = {};
+  int lplan[GPM_MAX_LAUNCH_STATS] = {};       // launch plan index (counter block)
+  int n_lstats = 0;
+  int n_launch_plans = 0;                     // counter blocks in h_res
   void* d_meta = nullptr;  size_t d_meta_bytes = 0;    // jobs, plans, offsets
   unsigned long long* d_res = nullptr; size_t d_res_words = 0;  // results + queues + counters
   int32_t* d_fbuf = nullptr; size_t d_fbuf_bytes = 0;
@@ -550,7 +555,7 @@ static int64_t kWedgeWaves(const gpm_ctx* c) { return (int64_t)c->cus * 8; }
 // scans, and its tile (plus the kernel's static LDS) within the workgroup's LDS.
 static int64_t lgs_block_max_vertices(const gpm_ctx* c) {
   int64_t d = kLgsBlockMaxVertices;
-  while (d > 0 && lgs_block_words(d) * 4 + 256 > (int64_t)c->lds_block_max) --d;
+  while (d > 0 && lgs_tile_words(d) * 4 + 256 > (int64_t)c->lds_block_max) --d;
   return d;
 }
 
@@ -777,7 +782,7 @@ static std::vector<std::pair<std::string, std::vector<int64_t>>> tune_space(cons
                                                                              int mode) {
   const bool clique = p.n_edges == p.k * (p.k - 1) / 2;
   if (clique && p.k <= 5)
-    return {{"lgs_tile", {128, 64, 192}}, {"waves_per_cu", {16, 12, 24}}, {"chunk", {0, 2}}};
+    return {{"lgs_tile", {128, 64, 192}}, {"waves_per_cu", {0, 16, 32}}, {"chunk", {0, 2}}};
   if (clique) return {{"lds_tile", {0, 256, 128}}, {"chunk", {0, 4, 16}}, {"waves_per_cu", {16, 12}}};
   (void)mode;
   return {{"leaf_cap", {128, 0, 32, 512}}, {"chunk", {0, 2, 32}}, {"granularity", {0, 1}},
@@ -897,6 +902,7 @@ static gpm_status slot_init(gpm_ctx* c, Slot& s, hipStream_t user) {
   }
   HIP_TRY(c, hipEventCreate(&s.ev0));
   HIP_TRY(c, hipEventCreate(&s.ev1));
+  for (auto& e : s.evl) HIP_TRY(c, hipEventCreate(&e));
   return GPM_OK;
 }
 
@@ -910,6 +916,8 @@ static void slot_free(Slot& s) {
   if (s.h_res) (void)hipHostFree(s.h_res);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
   if (s.ev1) (void)hipEventDestroy(s.ev1);
+  for (auto& e : s.evl)
+    if (e) (void)hipEventDestroy(e);
   if (s.stream && s.own_stream) (void)hipStreamDestroy(s.stream);
   s = Slot{};
 }
@@ -1034,7 +1042,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   int64_t blk_cap = 0;
   for (int i = 0; i < nj; ++i)
     if (jobs[i].kind == kJobCliqueLgsBlock) blk_cap = std::max<int64_t>(blk_cap, jobs[i].cap);
-  const size_t blk_lds = blk_cap ? (size_t)align_up((size_t)lgs_block_words(blk_cap), 4) * 4 : 0;
+  const size_t blk_lds = blk_cap ? (size_t)align_up((size_t)lgs_tile_words(blk_cap), 4) * 4 : 0;
   if (blk_cap && (blk_cap > kLgsBlockMaxVertices || blk_lds + 256 > (size_t)c->lds_block_max))
     return fail(c, GPM_E_DEVICE, "local graph exceeds the workgroup LDS");
 
@@ -1042,7 +1050,14 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   int64_t stride = 0;
   for (int i = 0; i < nj; ++i) stride = std::max(stride, need[i]);
   stride = (int64_t)align_up((size_t)stride, 64);
-  const int64_t wpc = c->opt_waves_per_cu > 0 ? c->opt_waves_per_cu : 16;
+  // auto: 24 waves per CU for the local-graph clique kernels (their register
+  // count allows six waves per SIMD), 16 otherwise
+  bool lgs_only = nj > 0;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].kind != kJobCliqueLgs && jobs[i].kind != kJobCliqueLgsBlock &&
+        jobs[i].kind != kJobClique)
+      lgs_only = false;
+  const int64_t wpc = c->opt_waves_per_cu > 0 ? c->opt_waves_per_cu : (lgs_only ? 24 : 16);
   int64_t max_resident = (int64_t)c->cus * wpc;
   int64_t waves = max_resident;
   if (stride > 0) {
@@ -1125,10 +1140,11 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     std::memcpy(h + off_jbeg[i], launches[i].jbeg.data(), 8 * launches[i].jbeg.size());
     std::memcpy(h + off_qbeg[i], launches[i].qbeg, 8 * (kQueues + 1));
   }
-  // device result words: results [nj * 8] | queues [launches * 8 * 16] | counters [4]
+  // device result words: results [nj * 8] | queues [launches * 8 * 16] |
+  // counters [launches * 4]
   const size_t res_words = (size_t)nj * kResultFields;
   const size_t q_words = launches.size() * kQueues * kQueueStride;
-  const size_t all_words = res_words + q_words + 4;
+  const size_t all_words = res_words + q_words + 4 * std::max<size_t>(launches.size(), 1);
   {
     size_t have = s.d_res_words * 8;
     st = grow_dev(c, (void**)&s.d_res, &have, all_words * 8);
@@ -1157,7 +1173,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     a.queue_begin = (const int64_t*)(dm + off_qbeg[i]);
     a.queue_cnt = s.d_res + res_words + i * kQueues * kQueueStride;
     a.results = s.d_res;
-    a.counters = s.d_res + res_words + q_words;
+    a.counters = s.d_res + res_words + q_words + 4 * i;
     a.fbuf = fbytes ? s.d_fbuf : nullptr;
     a.wave_stride = stride;
     const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs)) != 0;
@@ -1173,6 +1189,11 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     } else {
       e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
     }
+    if (!e && n_launch < GPM_MAX_LAUNCH_STATS) {
+      HIP_TRY(c, hipEventRecord(s.evl[n_launch], s.stream));
+      s.lkinds[n_launch] = L.kinds;
+      s.lplan[n_launch] = (int)i;
+    }
     if (e) return fail(c, GPM_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString((hipError_t)e));
     ++n_launch;
   }
@@ -1180,6 +1201,8 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   HIP_TRY(c, hipMemcpyAsync(s.h_res, s.d_res, all_words * 8, hipMemcpyDeviceToHost, s.stream));
   s.n_jobs = nj;
   s.n_launch = n_launch;
+  s.n_lstats = std::min(n_launch, GPM_MAX_LAUNCH_STATS);
+  s.n_launch_plans = (int)launches.size();
   s.counters_off = res_words + q_words;
   c->stats.waves = waves;
   c->stats.frontier_bytes = (int64_t)fbytes;
@@ -1197,11 +1220,27 @@ static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
   float ms = 0.f;
   if (s.n_launch > 0) HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
   c->stats.kernel_ms = ms;
+  c->stats.n_launch_stats = s.n_lstats;
+  for (int i = 0; i < s.n_lstats; ++i) {
+    float lm = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&lm, i ? s.evl[i - 1] : s.ev0, s.evl[i]));
+    c->stats.launch_ms[i] = lm;
+    c->stats.launch_kinds[i] = s.lkinds[i];
+    const unsigned long long* ct = s.h_res + s.counters_off + 4 * (size_t)s.lplan[i];
+    const bool on = c->opt_count_elements != 0;
+    c->stats.launch_elements[i] = on ? (int64_t)ct[0] : -1;
+    c->stats.launch_fetches[i] = on ? (int64_t)ct[1] : -1;
+    c->stats.launch_written[i] = on ? (int64_t)ct[2] : -1;
+    c->stats.launch_words[i] = on ? (int64_t)ct[3] : -1;
+  }
   if (c->opt_count_elements) {
-    c->stats.elements = (int64_t)s.h_res[s.counters_off];
-    c->stats.list_fetches = (int64_t)s.h_res[s.counters_off + 1];
-    c->stats.frontier_written = (int64_t)s.h_res[s.counters_off + 2];
-    c->stats.bitmap_words = (int64_t)s.h_res[s.counters_off + 3];
+    int64_t t[4] = {0, 0, 0, 0};
+    for (int i = 0; i < s.n_launch_plans; ++i)
+      for (int f = 0; f < 4; ++f) t[f] += (int64_t)s.h_res[s.counters_off + 4 * (size_t)i + f];
+    c->stats.elements = t[0];
+    c->stats.list_fetches = t[1];
+    c->stats.frontier_written = t[2];
+    c->stats.bitmap_words = t[3];
   }
   return GPM_OK;
 }

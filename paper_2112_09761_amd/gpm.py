@@ -63,6 +63,12 @@ class GraphMeta(ctypes.Structure):
                 ("max_out_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
+MAX_LAUNCH_STATS = 8   # GPM_MAX_LAUNCH_STATS
+# launch_kinds bits
+KIND_LGS_WAVE = 1 << 5
+KIND_LGS_BLOCK = 1 << 7
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("tasks", ctypes.c_int64), ("waves", ctypes.c_int64),
@@ -70,10 +76,21 @@ class Stats(ctypes.Structure):
                 ("list_fetches", ctypes.c_int64), ("frontier_written", ctypes.c_int64),
                 ("bitmap_words", ctypes.c_int64),
                 ("frontier_bytes", ctypes.c_int64),
-                ("launches", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("launches", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("n_launch_stats", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("launch_kinds", ctypes.c_uint32 * MAX_LAUNCH_STATS),
+                ("launch_ms", ctypes.c_double * MAX_LAUNCH_STATS),
+                ("launch_elements", ctypes.c_int64 * MAX_LAUNCH_STATS),
+                ("launch_fetches", ctypes.c_int64 * MAX_LAUNCH_STATS),
+                ("launch_written", ctypes.c_int64 * MAX_LAUNCH_STATS),
+                ("launch_words", ctypes.c_int64 * MAX_LAUNCH_STATS)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            d[f] = list(v)[:self.n_launch_stats] if f.startswith("launch_") else v
+        return d
 
 
 class PlanInfo(ctypes.Structure):

@@ -284,6 +284,35 @@ def test_workgroup_rmat_options(ctx, oracle):
         ctx.unload(gid)
 
 
+def test_per_launch_statistics(ctx):
+    """Per-launch statistics: one entry per launch in launch order, the
+    workgroup launch first, instrumented totals equal to the per-launch sums,
+    and launch durations that add up to the call's kernel time."""
+    from paper_2112_09761_amd import gpm
+    g = synth.rmat(13, 16, seed=1301)
+    gid = ctx.load(g)
+    try:
+        ctx.set_option("lgs_tile", 64)
+        ctx.set_option("count_elements", 1)
+        ctx.count(gid, synth_clique(5))
+        st = ctx.stats()
+        assert st["n_launch_stats"] == st["launches"] == 2
+        assert st["launch_kinds"] == [gpm.KIND_LGS_BLOCK, gpm.KIND_LGS_WAVE]
+        for f, tot in [("launch_elements", "elements"), ("launch_fetches", "list_fetches"),
+                       ("launch_written", "frontier_written"), ("launch_words", "bitmap_words")]:
+            assert sum(st[f]) == st[tot], f
+        assert all(x > 0 for x in st["launch_words"])
+        assert 0 < sum(st["launch_ms"]) <= st["kernel_ms"] * 1.001 + 0.01
+        ctx.set_option("count_elements", 0)
+        ctx.count(gid, synth_clique(4))
+        st = ctx.stats()
+        assert st["launch_elements"] == [-1, -1] and st["elements"] == -1
+    finally:
+        ctx.set_option("count_elements", 0)
+        ctx.set_option("lgs_tile", 128)
+        ctx.unload(gid)
+
+
 def test_workgroup_unordered_dag(ctx):
     """A DAG given by the caller whose orientation does not follow vertex ids
     (u -> v iff pi(u) < pi(v) for a random permutation pi): the workgroup

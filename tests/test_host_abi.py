@@ -31,6 +31,35 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(gpm.Query) == 16 + ctypes.sizeof(gpm.Pattern)
 
 
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct."""
+    import subprocess
+    structs = {"gpm_stats": gpm.Stats, "gpm_graph_meta": gpm.GraphMeta,
+               "gpm_plan_info": gpm.PlanInfo, "gpm_pattern": gpm.Pattern,
+               "gpm_query": gpm.Query}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gpm.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('return 0; }')
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o",
+                    str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, v = line.split()
+        got[(name, field)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
 def test_named_patterns():
     for name, (k, ne) in {"edge": (2, 1), "wedge": (3, 2), "triangle": (3, 3),
                           "path4": (4, 3), "star3": (4, 3), "cycle4": (4, 4),
