@@ -31,7 +31,8 @@ WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
 # for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
 # the kernel sources they were taken on (and that launch) only; else null.
-TRAFFIC = {"sources_sha256": "", "k": 5, "kinds": 1 << 7, "fetch_kib": 0.0, "write_kib": 0.0,
+TRAFFIC = {"sources_sha256": "ca9aabb5f962e183accd88a72df2e4f21180945528af2775818681ecae265440",
+           "k": 5, "kinds": 1 << 7, "fetch_kib": 1832344.4, "write_kib": 866.2,
            "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
 
