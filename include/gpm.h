@@ -165,6 +165,12 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     at most this long are counted one per lane (0 = off)
  *   "cycle4_algo"     edge-induced 4-cycles: 0/2 wedge aggregation, 1 the
  *                     DFS plan (identical counts)
+ *   "decompose"       1 (default) = wedge, 3-star, 4-path, tailed-triangle
+ *                     and diamond counts (both modes) come from per-vertex
+ *                     and per-edge terms (plus the 4-clique, triangle or
+ *                     4-cycle count their induced forms need: counting-only
+ *                     pruning, Sec. 5.4 (1)); 0 = the DFS plan (identical
+ *                     counts)
  *   "wedge_mem"       bytes of device memory the 4-cycle counter arrays may
  *                     use (default 16 GiB; fewer waves when exceeded)
  *   "budget"          device memory budget in bytes (as in gpm_create)

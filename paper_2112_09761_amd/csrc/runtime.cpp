@@ -94,6 +94,10 @@ struct QueryWork {
   int first_job = 0, n_jobs = 0;
   int clique_first = 0, clique_n = 0;   // motifs(4): jobs of the 4-clique count
   int cycle_first = 0, cycle_n = 0;     // motifs(4): jobs of the 4-cycle count
+  // counting-only decomposition of a single count (kDec*; 0 = none): the
+  // motif terms it reads (job slots relative to first_job, -1 if absent)
+  int dec = 0, dec_mode = 0;
+  int deg_slot = -1, edge_slot = -1;
   uint64_t constant = 0;   // result known on the host (k <= 2, n < k, ...)
   bool has_constant = false;
   int64_t ticket = -1;
@@ -148,6 +152,7 @@ struct gpm_ctx {
   int64_t opt_clique_algo = 0, opt_lgs_tile = 128, opt_lgs_max = kLgsMaxVertices;
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
   int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
+  int64_t opt_decompose = 1;                    // counting-only decomposition of named motifs
   int lds_block_max = 65536;                    // dynamic LDS per workgroup (bytes)
   int64_t opt_tune_min_ms = 20;
   int64_t opt_wedge_mem = int64_t(16) << 30;   // cap of the 4-cycle counter arrays
@@ -563,6 +568,89 @@ static int lds_tile(const gpm_ctx* c) {
   return c->opt_lds_tile > 0 ? (int)c->opt_lds_tile : 512;
 }
 
+// Named 3- and 4-vertex motifs whose count follows from per-vertex and
+// per-edge terms (counting-only pruning, Sec. 5.4 (1)).  For a connected
+// pattern the vertex count, edge count and largest degree identify the shape.
+enum { kDecNone = 0, kDecWedge, kDecStar3, kDecPath4, kDecTailed, kDecDiamond };
+
+static int decomposable(const gpm_pattern& p) {
+  int deg[kMaxK] = {0};
+  for (int i = 0; i < 2 * p.n_edges; ++i) deg[p.edges[i]]++;
+  int dmax = 0;
+  for (int i = 0; i < p.k; ++i) dmax = std::max(dmax, deg[i]);
+  if (p.k == 3 && p.n_edges == 2) return kDecWedge;
+  if (p.k == 4 && p.n_edges == 3) return dmax == 3 ? kDecStar3 : kDecPath4;
+  if (p.k == 4 && p.n_edges == 4 && dmax == 3) return kDecTailed;
+  if (p.k == 4 && p.n_edges == 5) return kDecDiamond;
+  return kDecNone;
+}
+
+static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int mode,
+                                 JobPlanSet& js, QueryWork& qw);
+static void named(const char* name, gpm_pattern* p);
+
+// Jobs of a decomposed count: the degree terms (ΣC(d,2), ΣC(d,3)), the edge
+// terms (Σt_e, ΣC(t_e,2), Σt_e(d_u+d_v−4), Σ(d_u−1)(d_v−1)) and, for the
+// vertex-induced counts, the 4-clique (triangle for the wedge) and 4-cycle
+// counts that the inclusion relation between the 4-vertex motifs needs.
+static gpm_status add_decomposed_jobs(gpm_ctx* c, Graph& g, int dec, int mode, JobPlanSet& js,
+                                      QueryWork& qw) {
+  const bool vi = mode == GPM_VERTEX_INDUCED;
+  const bool need_deg = dec == kDecWedge || dec == kDecStar3;
+  const bool need_edge = !(dec == kDecWedge || (dec == kDecStar3 && !vi));
+  qw.dec = dec;
+  qw.dec_mode = mode;
+  if (need_edge) {
+    gpm_status st = ensure_lower(c, g);
+    if (st) return st;
+  }
+  if (need_deg) {
+    Job J{};
+    J.kind = kJobVertexDeg;
+    J.rp = g.sym.rp;
+    J.col = g.sym.col;
+    J.vertex_tasks = 1;
+    J.n_tasks = g.host.n;
+    J.chunk = default_chunk(c, kJobVertexDeg);
+    qw.deg_slot = qw.n_jobs++;
+    js.jobs.push_back(J);
+    js.need_words.push_back(0);
+  }
+  if (need_edge) {
+    Job J{};
+    J.kind = kJobEdgeTri;
+    J.rp = g.sym.rp;
+    J.col = g.sym.col;
+    J.task_src = g.lo_src;
+    J.task_dst = g.lo_dst;
+    J.n_tasks = g.n_lo;
+    J.chunk = default_chunk(c, kJobEdgeTri);
+    qw.edge_slot = qw.n_jobs++;
+    js.jobs.push_back(J);
+    js.need_words.push_back(0);
+  }
+  if (vi) {
+    gpm_pattern p;
+    QueryWork tmp;
+    gpm_pattern_clique(dec == kDecWedge ? 3 : 4, &p);
+    qw.clique_first = qw.n_jobs;
+    gpm_status st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
+    if (st) return st;
+    qw.clique_n = tmp.n_jobs;  // 0 when the count is known to be 0
+    qw.n_jobs += tmp.n_jobs;
+    if (dec == kDecPath4) {
+      named("cycle4", &p);
+      tmp = QueryWork{};
+      qw.cycle_first = qw.n_jobs;
+      st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
+      if (st) return st;
+      qw.cycle_n = tmp.n_jobs;
+      qw.n_jobs += tmp.n_jobs;
+    }
+  }
+  return GPM_OK;
+}
+
 // Append the jobs counting `p` in `mode` on graph g; *constant set when the
 // answer needs no kernel.
 static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int mode,
@@ -684,6 +772,11 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     return GPM_OK;
   }
 
+  if (c->opt_decompose && !g.dag_only) {
+    const int dec = decomposable(p);
+    if (dec != kDecNone) return add_decomposed_jobs(c, g, dec, mode, js, qw);
+  }
+
   if (mode == GPM_EDGE_INDUCED && is_cycle4(p) && c->opt_cycle4_algo != 1) {
     st = ensure_wedge(c, g, kWedgeWaves(c));
     if (st) return st;
@@ -759,7 +852,6 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
   return GPM_OK;
 }
 
-static void named(const char* name, gpm_pattern* p);
 
 // ---------------------------------------------------------------------------
 // autotuner: task granularity, chunk size, LDS tile, waves per CU, leaf mode
@@ -862,8 +954,37 @@ static void finish_query(const QueryWork& qw, const unsigned long long* res, uin
     for (int j = 0; j < n; ++j) x += slot(first + j, 0);
     return x;
   };
-  if (qw.kind == GPM_QUERY_COUNT) {
+  if (qw.kind == GPM_QUERY_COUNT && qw.dec == kDecNone) {
     out[0] = sum0(0, qw.n_jobs);
+    return;
+  }
+  if (qw.kind == GPM_QUERY_COUNT) {
+    // decomposed count: non-induced counts from the terms, induced ones by
+    // the unitriangular inclusion relation of the 4-vertex motifs
+    auto f = [&](int s, int fld) { return s >= 0 ? slot(s, fld) : 0ull; };
+    const uint64_t sum_c2 = f(qw.deg_slot, 0), n_s3 = f(qw.deg_slot, 1);
+    const uint64_t three_t = f(qw.edge_slot, 0), n_d = f(qw.edge_slot, 1);
+    const uint64_t n_tt = f(qw.edge_slot, 2) / 2, pmid = f(qw.edge_slot, 3);
+    const uint64_t T = three_t / 3;
+    const bool vi = qw.dec_mode == GPM_VERTEX_INDUCED;
+    const uint64_t kc = sum0(qw.clique_first, qw.clique_n);  // triangles (wedge) or 4-cliques
+    const uint64_t i_d = n_d - 6 * kc, i_tt = n_tt - 4 * i_d - 12 * kc;
+    uint64_t r = 0;
+    switch (qw.dec) {
+      case kDecWedge: r = vi ? sum_c2 - 3 * kc : sum_c2; break;
+      case kDecDiamond: r = vi ? i_d : n_d; break;
+      case kDecTailed: r = vi ? i_tt : n_tt; break;
+      case kDecStar3: r = vi ? n_s3 - i_tt - 2 * i_d - 4 * kc : n_s3; break;
+      case kDecPath4: {
+        const uint64_t n_p4 = pmid - 3 * T;
+        if (!vi) { r = n_p4; break; }
+        const uint64_t i_c4 = sum0(qw.cycle_first, qw.cycle_n) - i_d - 3 * kc;
+        r = n_p4 - 4 * i_c4 - 2 * i_tt - 6 * i_d - 12 * kc;
+        break;
+      }
+      default: break;
+    }
+    out[0] = r;
     return;
   }
   const uint64_t sum_c2 = slot(0, 0), n_s3 = slot(0, 1);
@@ -1568,6 +1689,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
   else if (k == "lgs_block") c->opt_lgs_block = v != 0;
+  else if (k == "decompose") c->opt_decompose = v != 0;
   else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..2048"); c->opt_lgs_max = v; }

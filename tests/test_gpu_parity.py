@@ -164,7 +164,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                           ("granularity", [1]), ("clique_algo", [1, 2]),
                           ("lgs_tile", [64, 256]), ("lgs_max", [64, 100]),
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
-                          ("rename", [0]), ("cycle4_algo", [1, 2])]:
+                          ("rename", [0]), ("cycle4_algo", [1, 2]), ("decompose", [0])]:
             for v in vals:
                 ctx.set_option(opt, v)
                 for n, e in exp.items():
@@ -173,7 +173,8 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
             ctx.set_option(opt, {"chunk": 0, "waves_per_cu": 0, "lds_tile": 0,
                                  "clique_lds": 1, "granularity": 0, "clique_algo": 0,
                                  "lgs_tile": 128, "lgs_max": 2048, "lgs_split": 1,
-                                 "leaf_cap": 128, "rename": 1, "cycle4_algo": 0}[opt])
+                                 "leaf_cap": 128, "rename": 1, "cycle4_algo": 0,
+                                 "decompose": 1}[opt])
     finally:
         ctx.unload(gid)
 
@@ -401,7 +402,7 @@ def test_serving_alone_vs_mix(ctx, oracle):
             ctx.unload(gid)
 
 
-def test_error_paths_on_device(ctx):
+def test_error_paths_on_device(ctx, oracle):
     """Load-time validation, unknown ids, bad modes, unsupported patterns on a
     DAG-only graph, a memory budget too small for any frontier, and a full
     serving queue all return their status codes (no abort, no count)."""
@@ -429,14 +430,19 @@ def test_error_paths_on_device(ctx):
         ctx.count(did, "diamond", 1)
     assert e.value.status == -6
     ctx.unload(did)
-    # budget too small for even one wave's frontier
+    # budget too small for even one wave's frontier (the DFS plan stores a
+    # level; the decomposed count would need no frontier at all)
     ctx.set_option("budget", 1024)
+    ctx.set_option("decompose", 0)
     try:
         with pytest.raises(gpm.GpmError) as e:
             ctx.count(gid, "diamond", 1)
         assert e.value.status == -4
+        ctx.set_option("decompose", 1)
+        assert ctx.count(gid, "diamond", 1) == oracle.count(g, "diamond", False)
     finally:
         ctx.set_option("budget", 1 << 36)
+        ctx.set_option("decompose", 1)
     # serving: a full pending list says busy, the queued query still completes
     ctx.set_option("max_pending", 1)
     try:
