@@ -173,6 +173,9 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     counts)
  *   "wedge_mem"       bytes of device memory the 4-cycle counter arrays may
  *                     use (default 16 GiB; fewer waves when exceeded)
+ *   "wedge_list"      distinct wedge endpoints a 4-cycle task lists for its
+ *                     second pass (64..2^24, default 2^19); a task with more
+ *                     walks its wedges twice instead (identical counts)
  *   "budget"          device memory budget in bytes (as in gpm_create)
  *   "max_batch", "serve_slots", "max_pending"   serving limits
  *   "tune_min_ms"     autotuner threshold (see "autotune")

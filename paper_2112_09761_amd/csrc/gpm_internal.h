@@ -105,9 +105,10 @@ struct KernelArgs {
   int64_t wave_stride;             // int32 words of fbuf per wave
   int32_t lds_words;               // int32 words of dynamic LDS per wave
   int32_t lgs_tile;                // local graphs up to this size use LDS
-  int32_t pad;
+  int32_t zlist;                   // words at the end of each zbuf region: the
+                                   // list of a wedge task's distinct endpoints
   unsigned int* zbuf;              // per-wave counter arrays, zero between tasks
-  int64_t zstride;                 // words of zbuf per wave
+  int64_t zstride;                 // words of zbuf per wave (counters, then the list)
 };
 
 // Local-graph tile of T vertices, in int32 words: L[T] | P[T + 1] | (pad to

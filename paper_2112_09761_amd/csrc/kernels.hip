@@ -705,43 +705,63 @@ __device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
 // split across waves without any cross-task aggregation.
 // ---------------------------------------------------------------------------
 
+// One walk over the wedges v-u-w of a root (u over Nlo[0..e), w over the part
+// of N(u) in [a, b)).  The out-list offsets of each batch of 64 u's are staged
+// in S and their lengths' prefix in PF (LDS), so a wedge costs one search of
+// PF and one load of col.
+// Pass 1 (!SECOND): cnt[w] += 1; an endpoint seen for the first time is
+// appended to `list` (capacity cap); returns the number of distinct
+// endpoints (uniform; may exceed cap).
+// Pass 2 (SECOND, used when the list overflowed): takes every counter with an
+// atomic exchange (restoring zero) and returns Σ C(c_w, 2) (per lane).
 template <bool SECOND>
 __device__ __forceinline__ uint64_t wedge_pass(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col,
                                                const int32_t* Nlo, int32_t e, int32_t a,
-                                               int32_t b, unsigned int* cnt, int32_t* U,
-                                               int32_t* LO, int32_t* PF) {
+                                               int32_t b, unsigned int* cnt, int32_t* list,
+                                               int32_t cap, int64_t* S, int32_t* PF) {
   const int l = lane_id();
   uint64_t c = 0;
   for (int32_t ub = 0; ub < e; ub += 64) {
     const int32_t i = ub + l;
-    int32_t len = 0, lo = 0, u = 0;
+    int32_t len = 0;
+    int64_t start = 0;
     if (i < e) {
-      u = Nlo[i];
-      const int32_t* Nu = col + rp[u];
-      const int32_t du = (int32_t)(rp[u + 1] - rp[u]);
-      lo = lower_bound(Nu, du, a);
+      const int32_t u = Nlo[i];
+      const int64_t s0 = rp[u];
+      const int32_t* Nu = col + s0;
+      const int32_t du = (int32_t)(rp[u + 1] - s0);
+      const int32_t lo = lower_bound(Nu, du, a);
       len = lower_bound(Nu, du, b) - lo;
+      start = s0 + lo;
     }
     const int32_t incl = wave_incl_scan(len);
-    U[l] = u;
-    LO[l] = lo;
+    S[l] = start;
     PF[l] = incl;
     wave_sync_mem();
     const int32_t tot = uni(__shfl(incl, 63, 64));
     for (int32_t tb = 0; tb < tot; tb += 64) {
       const int32_t t = tb + l;
+      bool fresh = false;
+      int32_t w = 0;
       if (t < tot) {
         const int32_t o = upper_bound(PF, 64, t);
         const int32_t r = t - (o > 0 ? PF[o - 1] : 0);
-        const int32_t uu = U[o];
-        const int32_t w = col[rp[uu] + LO[o] + r];
+        w = col[S[o] + r];
         if (!SECOND) {
-          atomicAdd(&cnt[w], 1u);
+          fresh = atomicAdd(&cnt[w], 1u) == 0u;
         } else {
           const uint64_t x = (uint64_t)atomicExch(&cnt[w], 0u);
           c += x * (x - (x ? 1 : 0)) / 2;
         }
+      }
+      if (!SECOND) {
+        const uint64_t m = wave_ballot(fresh);
+        if (fresh) {
+          const uint64_t p = c + lanes_below(m);
+          if (p < (uint64_t)cap) list[p] = w;
+        }
+        c += (uint64_t)__popcll(m);
       }
     }
     wave_sync_mem();
@@ -1080,7 +1100,7 @@ gpm_persistent(KernelArgs a) {
   extern __shared__ int32_t lds[];
   __shared__ int32_t lds_state[kWavesPerBlock][2 * kMaxK];
   __shared__ int32_t dfs_defq[(KINDS & kKindDfs) ? kWavesPerBlock : 1][64];
-  __shared__ int32_t wedge_lds[(KINDS & kKindCycleWedge) ? kWavesPerBlock : 1][192];
+  __shared__ long long wedge_lds[(KINDS & kKindCycleWedge) ? kWavesPerBlock : 1][96];
   const int w = threadIdx.x >> 6;
   int32_t* my = lds + (size_t)w * a.lds_words;
   int32_t* st_words = lds_state[w];
@@ -1172,6 +1192,8 @@ gpm_persistent(KernelArgs a) {
     } else if ((KINDS & kKindCycleWedge) && kind == kJobCycleWedge) {
       nf = 1;
       unsigned int* cnt = a.zbuf + gw * a.zstride;
+      // the wave's region ends with its list of distinct endpoints
+      int32_t* list = (int32_t*)(cnt + a.zstride - a.zlist);
       for (int64_t t = t0; t < t1; ++t) {
         const int32_t v = uni(J.task_src[t]);
         int32_t part = 0, parts = 1;
@@ -1184,11 +1206,25 @@ gpm_persistent(KernelArgs a) {
         const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
         const int32_t a0 = (int32_t)((int64_t)v * part / parts);
         const int32_t b0 = (int32_t)((int64_t)v * (part + 1) / parts);
-        int32_t* U = wedge_lds[w];
-        wedge_pass<false>(rp, col, Nv, e, a0, b0, cnt, U, U + 64, U + 128);
-        // every counter update of pass 1 completes before pass 2 reads it
+        int64_t* S = (int64_t*)wedge_lds[w];
+        int32_t* PF = (int32_t*)(wedge_lds[w] + 64);
+        const int64_t nd =
+            uni64((int64_t)wedge_pass<false>(rp, col, Nv, e, a0, b0, cnt, list, a.zlist, S, PF));
+        // every counter update and list entry of pass 1 completes before pass 2 reads it
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        acc[0] += wedge_pass<true>(rp, col, Nv, e, a0, b0, cnt, U, U + 64, U + 128);
+        // pass 2; counters and list entries end at zero: the whole region is
+        // zero between tasks, whatever layout the next launch gives it
+        if (nd <= (int64_t)a.zlist) {
+          // over the distinct endpoints only
+          for (int64_t q = lane_id(); q < nd; q += 64) {
+            const uint64_t x = (uint64_t)atomicExch(&cnt[list[q]], 0u);
+            list[q] = 0;
+            acc[0] += x * (x - (x ? 1 : 0)) / 2;
+          }
+        } else {
+          acc[0] += wedge_pass<true>(rp, col, Nv, e, a0, b0, cnt, list, a.zlist, S, PF);
+          for (int32_t q = lane_id(); q < a.zlist; q += 64) list[q] = 0;
+        }
         if (CE) {
           ec.fetches += (uint64_t)e * 64;
         }

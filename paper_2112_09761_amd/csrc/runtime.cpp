@@ -153,6 +153,7 @@ struct gpm_ctx {
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
   int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
   int64_t opt_decompose = 1;                    // counting-only decomposition of named motifs
+  int64_t opt_wedge_list = 1 << 19;             // distinct-endpoint list per 4-cycle wave
   int lds_block_max = 65536;                    // dynamic LDS per workgroup (bytes)
   int64_t opt_tune_min_ms = 20;
   int64_t opt_wedge_mem = int64_t(16) << 30;   // cap of the 4-cycle counter arrays
@@ -895,9 +896,8 @@ static gpm_status add_motif_jobs(gpm_ctx* c, Graph& g, int k, JobPlanSet& js, Qu
   qw.kind = GPM_QUERY_MOTIFS;
   qw.k = k;
   if (g.m == 0) { qw.has_constant = true; qw.constant = 0; return GPM_OK; }
-  gpm_status st = ensure_lower(c, g);
-  if (st) return st;
-  // slot order: [degree terms] [edge terms] [clique] [cycle4]
+  gpm_status st = GPM_OK;
+  // slot order: [degree terms] [edge terms (k = 4)] [clique] [cycle4]
   {
     Job J{};
     J.kind = kJobVertexDeg;
@@ -909,6 +909,21 @@ static gpm_status add_motif_jobs(gpm_ctx* c, Graph& g, int k, JobPlanSet& js, Qu
     js.jobs.push_back(J);
     js.need_words.push_back(0);
   }
+  qw.n_jobs += 1;
+  if (k == 3) {
+    // the triangle count alone: the local-graph clique kernel
+    gpm_pattern p;
+    QueryWork tmp;
+    gpm_pattern_clique(3, &p);
+    qw.clique_first = (int)js.jobs.size() - qw.first_job;
+    st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
+    if (st) return st;
+    qw.clique_n = tmp.n_jobs;
+    qw.n_jobs += tmp.n_jobs;
+    return GPM_OK;
+  }
+  st = ensure_lower(c, g);
+  if (st) return st;
   {
     Job J{};
     J.kind = kJobEdgeTri;
@@ -921,7 +936,7 @@ static gpm_status add_motif_jobs(gpm_ctx* c, Graph& g, int k, JobPlanSet& js, Qu
     js.jobs.push_back(J);
     js.need_words.push_back(0);
   }
-  qw.n_jobs += 2;
+  qw.n_jobs += 1;
   if (k == 4) {
     gpm_pattern p;
     QueryWork tmp;
@@ -988,13 +1003,14 @@ static void finish_query(const QueryWork& qw, const unsigned long long* res, uin
     return;
   }
   const uint64_t sum_c2 = slot(0, 0), n_s3 = slot(0, 1);
-  const uint64_t three_t = slot(1, 0), n_d = slot(1, 1), two_tt = slot(1, 2), pmid = slot(1, 3);
-  const uint64_t T = three_t / 3;
   if (qw.k == 3) {
+    const uint64_t T = sum0(qw.clique_first, qw.clique_n);
     out[0] = sum_c2 - 3 * T;  // induced wedges
     out[1] = T;
     return;
   }
+  const uint64_t three_t = slot(1, 0), n_d = slot(1, 1), two_tt = slot(1, 2), pmid = slot(1, 3);
+  const uint64_t T = three_t / 3;
   // non-induced 4-vertex counts -> induced (unitriangular inclusion relation)
   const uint64_t n_k4 = sum0(qw.clique_first, qw.clique_n);
   const uint64_t n_c4 = sum0(qw.cycle_first, qw.cycle_n);
@@ -1192,6 +1208,11 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   for (int i = 0; i < nj; ++i)
     if (jobs[i].kind == kJobCycleWedge) zstride = std::max<int64_t>(zstride, jobs[i].cap);
   zstride = (int64_t)align_up((size_t)zstride, 64);
+  // plus the list of a task's distinct endpoints (a task with more falls back
+  // to a second walk over its wedges)
+  const int64_t zlist =
+      zstride ? (int64_t)align_up((size_t)std::min<int64_t>(zstride, c->opt_wedge_list), 64) : 0;
+  zstride += zlist;
   if (zstride) {
     waves = std::min<int64_t>(waves, kWedgeWaves(c));
     const int64_t left = std::min<int64_t>((int64_t)frontier_budget - waves * stride * 4,
@@ -1302,6 +1323,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     a.lgs_tile = lgs_T;
     a.zbuf = (L.kinds & kKindCycleWedge) ? s.d_zero : nullptr;
     a.zstride = zstride;
+    a.zlist = (int32_t)zlist;
     size_t lb = uses_lds ? lds_bytes : 0;
     int e;
     if (L.kinds == kKindCliqueLgsBlock) {
@@ -1690,6 +1712,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
   else if (k == "lgs_block") c->opt_lgs_block = v != 0;
   else if (k == "decompose") c->opt_decompose = v != 0;
+  else if (k == "wedge_list") { if (v < 64 || v > (1 << 24)) return fail(c, GPM_E_INVAL, "wedge_list 64..2^24"); c->opt_wedge_list = v; }
   else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..2048"); c->opt_lgs_max = v; }

@@ -337,6 +337,29 @@ def test_workgroup_unordered_dag(ctx):
         ctx.unload(did)
 
 
+def test_wedge_counters_across_layouts(ctx, oracle):
+    """4-cycle counter arrays are laid out per launch by the largest graph's
+    vertex count; interleaving graphs of different sizes (and motif queries
+    that share the launch with other kinds) must never see a stale counter or
+    list entry, with the distinct-endpoint list large or overflowing."""
+    gs = [synth.rmat(12, 8, seed=1401), synth.grid(5, 7), synth.complete(9),
+          synth.rmat(10, 8, seed=1402), synth.chung_lu(3000, 8.0, 2.1, 300.0, 12000, 1403)]
+    ids = [ctx.load(g) for g in gs]
+    exp_c4 = [oracle.cycle4(g) for g in gs]
+    exp_m4 = [oracle.motifs4(g) for g in gs]
+    try:
+        for cap in (64, 1 << 19, 64):
+            ctx.set_option("wedge_list", cap)
+            for rep in range(2):
+                for i in ([0, 1, 2, 3, 4] if rep == 0 else [4, 2, 0, 3, 1]):
+                    assert ctx.count(ids[i], "cycle4", E) == exp_c4[i], (cap, i)
+                    assert ctx.motifs(ids[i], 4) == exp_m4[i], (cap, i)
+    finally:
+        ctx.set_option("wedge_list", 1 << 19)
+        for gid in ids:
+            ctx.unload(gid)
+
+
 def test_edge_cases(ctx):
     from paper_2112_09761_amd import gpm
     e = synth.empty(10)
