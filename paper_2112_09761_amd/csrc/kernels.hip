@@ -322,26 +322,37 @@ __device__ __forceinline__ int32_t lgs_hash_get(const TH* H, int32_t bits, int32
 // the hash H of L).  Out-lists are sorted, so a row stops at the first batch
 // whose elements all exceed max(L).  With BITS the hits are set in R (rows
 // of W words); the number of hits is returned either way (per lane).
+// With `next` (the workgroup path), rows are taken from that LDS counter one
+// at a time instead (first and step unused), so waves that drew short rows
+// take more of them.
 template <bool CE, bool BITS, typename TL, typename TH, typename TR>
 __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const TL* L,
                                                    int32_t d, int32_t W, const TH* H,
                                                    int32_t bits, TR* R, int32_t first,
-                                                   int32_t step, ElemCounter& ec) {
+                                                   int32_t step, ElemCounter& ec,
+                                                   int32_t* next = nullptr) {
   constexpr int U = 4;  // batches of 64 elements whose loads are in flight together
   const int l = lane_id();
   const int32_t lmax = uni(L[d - 1]);
+  auto take = [&]() -> int32_t {
+    int32_t r = 0;
+    if (l == 0) r = atomicAdd(next, 1);
+    return uni(__shfl(r, 0, 64));
+  };
   uint64_t hits = 0;
+  int32_t i = next ? take() : first;
   int64_t nb = 0, ne = 0;  // bounds of the next row, loaded one row ahead
-  if (first < d) {
-    const int32_t v = uni(L[first]);
+  if (i < d) {
+    const int32_t v = uni(L[i]);
     nb = uni64(rp[v]);
     ne = uni64(rp[v + 1]);
   }
-  for (int32_t i = first; i < d; i += step) {
+  while (i < d) {
     const int64_t b = nb, e = ne;
-    if (i + step < d) {
-      const int32_t v = uni(L[i + step]);
+    const int32_t in = next ? take() : i + step;
+    if (in < d) {
+      const int32_t v = uni(L[in]);
       nb = uni64(rp[v]);
       ne = uni64(rp[v + 1]);
     }
@@ -366,6 +377,7 @@ __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ r
       // out-lists are sorted: once every element exceeds max(L), none further can hit
       if (wave_ballot(x[U - 1] <= lmax) == 0ull) break;
     }
+    i = in;
   }
   return hits;
 }
@@ -403,17 +415,24 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
     // the pair's count fits 32 bits (|M| * d < 2^22): popcount-accumulate
     uint32_t cp = 0;
     if constexpr (WC <= 16) {
-      // both loops unrolled: every word index is static
+      // both loops unrolled: every word index is static.  Bits are taken from
+      // the two 32-bit halves of each word (cheaper find-first and clear), and
+      // the row index is kept opaque so the row's reads share one base
+      // address with small immediate offsets.
 #pragma unroll
       for (int x = 0; x < WC; ++x) {
-        uint64_t m = M[x];
-        while (m) {
-          const int b = __builtin_ctzll(m);
-          m &= m - 1ull;
-          const TR* Rl = R + (size_t)(x * 64 + b) * WC;
 #pragma unroll
-          for (int y = ORD ? x : 0; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
-          if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
+        for (int h = 0; h < 2; ++h) {
+          uint32_t m = (uint32_t)(M[x] >> (32 * h));
+          while (m) {
+            int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
+            m &= m - 1u;
+            asm volatile("" : "+v"(lrow));
+            const TR* Rl = R + (size_t)lrow * WC;
+#pragma unroll
+            for (int y = ORD ? x : 0; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
+            if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
+          }
         }
       }
     } else {
@@ -582,10 +601,10 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* tmp, int3
 // workgroup (rows dealt round-robin to its waves) and the tile (T = d) in
 // its LDS.  Every thread returns its partial count.
 template <bool CE>
-__device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
+__device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
                                      const int32_t* __restrict__ col, int k, int32_t u,
                                      int32_t d, int32_t part, int32_t parts, bool ordered,
-                                     int32_t* lds, int32_t* tmp, ElemCounter& ec) {
+                                     int32_t* lds, int32_t* tmp, int32_t* next, ElemCounter& ec) {
   constexpr int NT = kBlockWaves * 64;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
@@ -604,6 +623,7 @@ __device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
     v = Nu[tid];
     L[tid] = v;
   }
+  if (tid == 0) *next = 0;
   __syncthreads();
   if (tid < d) lgs_hash_put(H, bits, v, tid);
   __syncthreads();
@@ -613,9 +633,10 @@ __device__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
   }
   // k = 3: every hit is a triangle at this root
   if (k == 3)
-    return part == 0 ? lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec)
-                     : 0;
-  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec);
+    return part == 0
+               ? lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next)
+               : 0;
+  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next);
   __syncthreads();
   uint64_t c = 0;
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
@@ -1312,6 +1333,7 @@ __global__ void __launch_bounds__(kBlockWaves * 64)
 gpm_lgs_block(KernelArgs a) {
   extern __shared__ __attribute__((aligned(16))) int32_t blk_lds[];
   __shared__ int32_t scan_tmp[kBlockWaves];
+  __shared__ int32_t row_next;
   __shared__ long long chunk_lds;
   const int home = (int)(blockIdx.x & (kQueues - 1));
   uint32_t dead = 0;
@@ -1347,7 +1369,7 @@ gpm_lgs_block(KernelArgs a) {
         parts = enc >> 16;
       }
       acc[0] += clique_lgs_block<CE>(J.rp, J.col, J.k, u, d, part, parts, J.ordered != 0,
-                                     blk_lds, scan_tmp, ec);
+                                     blk_lds, scan_tmp, &row_next, ec);
       __syncthreads();  // the next root reuses the local graph's LDS
     }
   }
