@@ -428,7 +428,8 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
             int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
             m &= m - 1u;
             asm volatile("" : "+v"(lrow));
-            const TR* Rl = R + (size_t)lrow * WC;
+            // rows < 2^24: the 24-bit multiply is exact and full rate
+            const TR* Rl = R + __umul24((uint32_t)lrow, (uint32_t)WC);
 #pragma unroll
             for (int y = ORD ? x : 0; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
             if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
