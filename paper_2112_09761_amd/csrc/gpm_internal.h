@@ -68,6 +68,12 @@ constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVerte
 constexpr int kLgsMaxVertices = 2048;   // local graphs handled by the bitmap kernel
 constexpr int kBlockWaves = 16;         // workgroup of the large-root kernel (1024 threads)
 constexpr int kLgsBlockMaxVertices = kBlockWaves * 64;  // one vertex per thread in its scans
+// The workgroup kernel sorts its 5-clique local edges by cost in batches of
+// kSortBatch per wave: an LDS area of kSortBatch ids and 64 bucket counters
+// per wave, after the largest tile of the launch.
+constexpr int kSortBatch = 256;
+constexpr int kSortWords = kSortBatch + 64;
+constexpr int kBlockSortWords = kBlockWaves * kSortWords;
 
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
 // root tasks) triple with its own result slot.

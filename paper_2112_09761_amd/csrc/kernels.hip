@@ -457,6 +457,107 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
   return c;
 }
 
+// 5-clique count of one local edge (i, j) of an ordered local graph with rows
+// of WC words: Σ_{l ∈ M} |M ∩ R_l|, M = R_i & R_j (bits above j only).
+template <int WC>
+__device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32_t i, int32_t j) {
+  const unsigned long long* Ri = R + (size_t)i * WC;
+  const unsigned long long* Rj = R + (size_t)j * WC;
+  const int jw = (j + 1) >> 6;
+  uint64_t M[WC];
+#pragma unroll
+  for (int x = 0; x < WC; ++x) M[x] = (x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
+  uint32_t cp = 0;
+#pragma unroll
+  for (int x = 0; x < WC; ++x) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t m = (uint32_t)(M[x] >> (32 * h));
+      while (m) {
+        int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
+        m &= m - 1u;
+        asm volatile("" : "+v"(lrow));
+        const unsigned long long* Rl = R + __umul24((uint32_t)lrow, (uint32_t)WC);
+#pragma unroll
+        for (int y = x; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
+      }
+    }
+  }
+  return cp;
+}
+
+// The workgroup kernel's 5-clique pair phase with lanes balanced by work:
+// each wave takes batches of kSortBatch consecutive local edges (p0 .. p1-1,
+// enumerated through the row-size prefix P), keys every edge by a
+// logarithm of its cost estimate |R_i & R_j| · (words from j's on) — four
+// keys per octave, 0..63 — counting-sorts the batch by key in its LDS area
+// (ids, cnt), then counts the sorted edges 64 at a time, so that the lanes of
+// a round hold edges of similar cost.  Returns this thread's partial count.
+template <int WC>
+__device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
+                                                      const unsigned long long* R, int32_t d,
+                                                      int32_t p0, int32_t p1, int32_t* ids,
+                                                      int32_t* cnt) {
+  constexpr int K = kSortBatch / 64;
+  const int l = lane_id();
+  const int wv = threadIdx.x >> 6;
+  uint64_t c = 0;
+  for (int32_t base = p0 + wv * kSortBatch; base < p1; base += kBlockWaves * kSortBatch) {
+    cnt[l] = 0;
+    wave_sync_mem();
+    int32_t key[K], pid[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int32_t t = base + q * 64 + l;
+      key[q] = 64;
+      pid[q] = 0;
+      if (t < p1) {
+        const int32_t i = upper_bound(P + 1, d, t);
+        int32_t r = t - P[i];
+        const unsigned long long* Ri = R + (size_t)i * WC;
+        int32_t w = 0;
+        for (;; ++w) {
+          const int32_t pc = __popcll(Ri[w]);
+          if (r < pc) break;
+          r -= pc;
+        }
+        const int32_t j = w * 64 + select64(Ri[w], r);
+        const unsigned long long* Rj = R + (size_t)j * WC;
+        const int jw = (j + 1) >> 6;
+        int32_t m = 0;
+#pragma unroll
+        for (int x = 0; x < WC; ++x)
+          if (x >= jw) m += __popcll(Ri[x] & Rj[x]);
+        const int32_t v = min(m * (WC - jw), 65535);
+        key[q] = v < 4 ? v : ((31 - __clz(v)) << 2) | ((v >> (29 - __clz(v))) & 3);
+        pid[q] = (i << 16) | j;
+        atomicAdd(&cnt[key[q]], 1);
+      }
+    }
+    wave_sync_mem();
+    // exclusive prefix over the 64 buckets, one per lane
+    const int32_t cb = cnt[l];
+    const int32_t incl = wave_incl_scan(cb);
+    const int32_t nvalid = uni(__shfl(incl, 63, 64));
+    cnt[l] = incl - cb;
+    wave_sync_mem();
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+      if (key[q] < 64) ids[atomicAdd(&cnt[key[q]], 1)] = pid[q];
+    wave_sync_mem();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int32_t idx = q * 64 + l;
+      if (idx < nvalid) {
+        const int32_t e = ids[idx];
+        c += lgs_edge5<WC>(R, e >> 16, e & 0xffff);
+      }
+    }
+    wave_sync_mem();  // the next batch reuses ids and cnt
+  }
+  return c;
+}
+
 template <bool CE, typename TL, typename TP, typename TH, typename TR>
 __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
@@ -605,7 +706,8 @@ template <bool CE>
 __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
                                      const int32_t* __restrict__ col, int k, int32_t u,
                                      int32_t d, int32_t part, int32_t parts, bool ordered,
-                                     int32_t* lds, int32_t* tmp, int32_t* next, ElemCounter& ec) {
+                                     int32_t* lds, int32_t* tmp, int32_t* next, int32_t* sort_area,
+                                     ElemCounter& ec) {
   constexpr int NT = kBlockWaves * 64;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
@@ -673,10 +775,12 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
     return c;
   }
   if (!CE && ordered) {
+    int32_t* ids = sort_area + (size_t)wv * kSortWords;
+    int32_t* bcnt = ids + kSortBatch;
     switch (W) {
 #define GPM_LGSB5(WC) \
   case WC:            \
-    return lgs_pairs5<false, WC, true>(P, R, d, p0, p1, tid, NT, ec);
+    return lgs_pairs5_sorted<WC>(P, R, d, p0, p1, ids, bcnt);
       GPM_LGSB5(1) GPM_LGSB5(2) GPM_LGSB5(3) GPM_LGSB5(4) GPM_LGSB5(5) GPM_LGSB5(6)
       GPM_LGSB5(7) GPM_LGSB5(8) GPM_LGSB5(9) GPM_LGSB5(10) GPM_LGSB5(11) GPM_LGSB5(12)
       GPM_LGSB5(13) GPM_LGSB5(14) GPM_LGSB5(15) GPM_LGSB5(16)
@@ -1369,8 +1473,10 @@ gpm_lgs_block(KernelArgs a) {
         part = enc & 0xffff;
         parts = enc >> 16;
       }
+      // the edge-sorting area follows the largest tile of the launch
       acc[0] += clique_lgs_block<CE>(J.rp, J.col, J.k, u, d, part, parts, J.ordered != 0,
-                                     blk_lds, scan_tmp, &row_next, ec);
+                                     blk_lds, scan_tmp, &row_next,
+                                     blk_lds + a.lds_words - kBlockWaves * kSortWords, ec);
       __syncthreads();  // the next root reuses the local graph's LDS
     }
   }

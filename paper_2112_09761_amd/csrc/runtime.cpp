@@ -561,7 +561,9 @@ static int64_t kWedgeWaves(const gpm_ctx* c) { return (int64_t)c->cus * 8; }
 // scans, and its tile (plus the kernel's static LDS) within the workgroup's LDS.
 static int64_t lgs_block_max_vertices(const gpm_ctx* c) {
   int64_t d = kLgsBlockMaxVertices;
-  while (d > 0 && lgs_tile_words(d) * 4 + 256 > (int64_t)c->lds_block_max) --d;
+  while (d > 0 && (((lgs_tile_words(d) + 3) & ~int64_t(3)) + kBlockSortWords) * 4 + 256 >
+                      (int64_t)c->lds_block_max)
+    --d;
   return d;
 }
 
@@ -1179,7 +1181,8 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   int64_t blk_cap = 0;
   for (int i = 0; i < nj; ++i)
     if (jobs[i].kind == kJobCliqueLgsBlock) blk_cap = std::max<int64_t>(blk_cap, jobs[i].cap);
-  const size_t blk_lds = blk_cap ? (size_t)align_up((size_t)lgs_tile_words(blk_cap), 4) * 4 : 0;
+  const size_t blk_lds =
+      blk_cap ? ((size_t)align_up((size_t)lgs_tile_words(blk_cap), 4) + kBlockSortWords) * 4 : 0;
   if (blk_cap && (blk_cap > kLgsBlockMaxVertices || blk_lds + 256 > (size_t)c->lds_block_max))
     return fail(c, GPM_E_DEVICE, "local graph exceeds the workgroup LDS");
 
