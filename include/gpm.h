@@ -154,7 +154,7 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *   "lgs_tile"        local graphs up to this many vertices stay in one
  *                     wave's LDS (64..256, default 128)
  *   "lgs_block"       1 (default) = larger local graphs that fit a
- *                     workgroup's LDS (up to 960 vertices with 160 KB, fewer when the
+ *                     workgroup's LDS (up to 896 vertices with 160 KB, fewer when the
  *                     device's per-workgroup LDS is smaller) are searched by
  *                     a whole workgroup each; 0 = by one wave, rows in HBM
  *   "lgs_max"         roots with more out-neighbours (64..2048) use the

@@ -71,7 +71,7 @@ constexpr int kLgsBlockMaxVertices = kBlockWaves * 64;  // one vertex per thread
 // The workgroup kernel sorts its 5-clique local edges by cost in batches of
 // kSortBatch per wave: an LDS area of kSortBatch ids and 64 bucket counters
 // per wave, after the largest tile of the launch.
-constexpr int kSortBatch = 256;
+constexpr int kSortBatch = 512;
 constexpr int kSortWords = kSortBatch + 64;
 constexpr int kBlockSortWords = kBlockWaves * kSortWords;
 

@@ -234,13 +234,13 @@ def test_esym_closed_form():
 @pytest.mark.parametrize("parts,k5_both", [
     ([1] * 65, True),                 # K_65: out-degrees 0..64
     ([3] * 97 + [1] * 10, True),      # n = 301, ragged rows
-    ([1] * 961, False),               # K_961: the largest workgroup root, d = 960
+    ([1] * 897, False),               # K_897: the largest workgroup root, d = 896
     ([1] * 1025, False),              # K_1025: roots just above the workgroup limit
     ([2] * 550, False),               # n = 1100: roots above the workgroup limit too
 ])
 def test_workgroup_local_graphs(ctx, parts, k5_both):
     """Roots with more out-neighbours than the per-wave tile are searched by a
-    whole workgroup (up to 960 out-neighbours with 160 KB of LDS per
+    whole workgroup (up to 896 out-neighbours with 160 KB of LDS per
     workgroup); larger ones by one wave with rows in HBM.  Dense multipartite
     graphs put roots in all three ranges; every count must equal the closed
     form, with the workgroup path on and off."""
