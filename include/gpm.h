@@ -173,6 +173,11 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     counts)
  *   "wedge_mem"       bytes of device memory the 4-cycle counter arrays may
  *                     use (default 16 GiB; fewer waves when exceeded)
+ *   "edge_terms"      per-edge motif terms (4-motifs, decomposed counts):
+ *                     0 (default) = the k = 3 local-graph search adds each
+ *                     triangle to its three edges' counters, then one pass
+ *                     over the edges; 1 = one list intersection per edge
+ *                     (identical counts)
  *   "wedge_list"      distinct wedge endpoints a 4-cycle task lists for its
  *                     second pass (64..2^24, default 2^19); a task with more
  *                     walks its wedges twice instead (identical counts)

@@ -53,6 +53,7 @@ enum JobKind : int32_t {
   kJobCycleWedge = 6,  // edge-induced 4-cycles by wedge aggregation
   kJobCliqueLgsBlock = 7,  // k-clique (k = 3..5): the local graph of one large
                            // root shared by a whole workgroup (own kernel)
+  kJobEdgeTerms = 8,   // per-edge motif terms from per-edge triangle counts
 };
 
 constexpr uint32_t kKindClique = 1u << kJobClique;
@@ -62,9 +63,10 @@ constexpr uint32_t kKindVertexDeg = 1u << kJobVertexDeg;
 constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
 constexpr uint32_t kKindCycleWedge = 1u << kJobCycleWedge;
 constexpr uint32_t kKindCliqueLgsBlock = 1u << kJobCliqueLgsBlock;
+constexpr uint32_t kKindEdgeTerms = 1u << kJobEdgeTerms;
 // kinds of the per-wave persistent kernel (the workgroup kernel has its own)
 constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg |
-                              kKindCliqueLgs | kKindCycleWedge;
+                              kKindCliqueLgs | kKindCycleWedge | kKindEdgeTerms;
 constexpr int kLgsMaxVertices = 2048;   // local graphs handled by the bitmap kernel
 constexpr int kBlockWaves = 16;         // workgroup of the large-root kernel (1024 threads)
 constexpr int kLgsBlockMaxVertices = kBlockWaves * 64;  // one vertex per thread in its scans
@@ -95,6 +97,13 @@ struct Job {
   int32_t ordered;         // clique job: out-lists follow the orientation order
                            // (u -> v iff u < v), so local bitmap rows are
                            // upper triangular
+  int32_t tri_group;       // > 0: triangle-scatter group.  Its k = 3 local-graph
+                           // jobs add 1 per triangle to each of its three edges'
+                           // counters (indexed by DAG position) instead of
+                           // counting; its kJobEdgeTerms job reads them
+  unsigned int* tri;       // the group's per-DAG-edge counters (set at launch;
+                           // zero between launches)
+  const int64_t* deg_rp;   // kJobEdgeTerms: offsets of the symmetric graph (degrees)
 };
 
 struct KernelArgs {

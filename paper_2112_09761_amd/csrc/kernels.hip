@@ -324,14 +324,18 @@ __device__ __forceinline__ int32_t lgs_hash_get(const TH* H, int32_t bits, int32
 // of W words); the number of hits is returned either way (per lane).
 // With `next` (the workgroup path), rows are taken from that LDS counter one
 // at a time instead (first and step unused), so waves that drew short rows
-// take more of them.
-template <bool CE, bool BITS, typename TL, typename TH, typename TR>
+// take more of them.  With SC every hit (triangle u, L[i], L[j]) adds 1 to
+// the per-row counters lc[i] and lc[j] (edges u-L[i], u-L[j]) and to
+// tri[p], p the DAG position of the element (edge L[i]-L[j]).
+template <bool CE, bool BITS, bool SC = false, typename TL, typename TH, typename TR,
+          typename TC = int32_t>
 __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const TL* L,
                                                    int32_t d, int32_t W, const TH* H,
                                                    int32_t bits, TR* R, int32_t first,
                                                    int32_t step, ElemCounter& ec,
-                                                   int32_t* next = nullptr) {
+                                                   int32_t* next = nullptr, TC* lc = nullptr,
+                                                   unsigned int* tri = nullptr) {
   constexpr int U = 4;  // batches of 64 elements whose loads are in flight together
   const int l = lane_id();
   const int32_t lmax = uni(L[d - 1]);
@@ -371,6 +375,11 @@ __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ r
           if (j >= 0) {
             ++hits;
             if (BITS) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
+            if (SC) {
+              atomicAdd(&lc[i], 1);
+              atomicAdd(&lc[j], 1);
+              atomicAdd(&tri[pb + q * 64 + l], 1u);
+            }
           }
         }
       }
@@ -563,7 +572,8 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
                                                int32_t u, int32_t d, int32_t part,
                                                int32_t parts, bool ordered, TL* L, TP* P,
-                                               TH* H, TR* R, ElemCounter& ec) {
+                                               TH* H, TR* R, unsigned int* tri,
+                                               ElemCounter& ec) {
   const int l = lane_id();
   const int32_t W = (d + 63) >> 6;
   const int32_t bits = lgs_hash_bits(d);
@@ -580,8 +590,19 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
     ec.fetches += (uint64_t)d + 1;
   }
   // k = 3: every hit is a triangle at this root
-  if (k == 3)
-    return part == 0 ? lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec) : 0;
+  if (k == 3) {
+    if (part != 0) return 0;
+    if (!tri) return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
+    // triangle scatter: P holds the per-row counters (edges u-L[i])
+    for (int32_t i = l; i < d; i += 64) P[i] = 0;
+    wave_sync_mem();
+    lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr, P, tri);
+    wave_sync_mem();
+    const int64_t e0 = rp[u];
+    for (int32_t i = l; i < d; i += 64)
+      if (P[i]) atomicAdd(&tri[e0 + i], (unsigned int)P[i]);
+    return 0;
+  }
   lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
   wave_sync_mem();
   uint64_t c = 0;
@@ -707,7 +728,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
                                      const int32_t* __restrict__ col, int k, int32_t u,
                                      int32_t d, int32_t part, int32_t parts, bool ordered,
                                      int32_t* lds, int32_t* tmp, int32_t* next, int32_t* sort_area,
-                                     ElemCounter& ec) {
+                                     unsigned int* tri, ElemCounter& ec) {
   constexpr int NT = kBlockWaves * 64;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
@@ -735,10 +756,21 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
     ec.fetches += (uint64_t)d + 1;
   }
   // k = 3: every hit is a triangle at this root
-  if (k == 3)
-    return part == 0
-               ? lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next)
-               : 0;
+  if (k == 3) {
+    if (part != 0) return 0;
+    if (!tri)
+      return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next);
+    // triangle scatter: P holds the per-row counters (edges u-L[i])
+    for (int32_t i = tid; i < d; i += NT) P[i] = 0;
+    __syncthreads();
+    lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next, P,
+                                    tri);
+    __syncthreads();
+    const int64_t e0 = rp[u];
+    for (int32_t i = tid; i < d; i += NT)
+      if (P[i]) atomicAdd(&tri[e0 + i], (unsigned int)P[i]);
+    return 0;
+  }
   lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next);
   __syncthreads();
   uint64_t c = 0;
@@ -1305,14 +1337,14 @@ gpm_persistent(KernelArgs a) {
           unsigned long long* H = (unsigned long long*)(my + lgs_hash_offset(a.lgs_tile));
           unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
           acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
-                                   ec);
+                                   J.tri, ec);
         } else {
           int32_t* L = fb;
           int32_t* Pp = fb + J.cap;
           unsigned long long* H = (unsigned long long*)(fb + lgs_hash_offset(J.cap));
           unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
           acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
-                                   ec);
+                                   J.tri, ec);
         }
       }
     } else if ((KINDS & kKindCycleWedge) && kind == kJobCycleWedge) {
@@ -1405,6 +1437,21 @@ gpm_persistent(KernelArgs a) {
           acc[3] += (uint64_t)(du - 1) * (uint64_t)(dv - 1);
         }
       }
+    } else if ((KINDS & kKindEdgeTerms) && kind == kJobEdgeTerms) {
+      // per DAG edge e = (u, v) with its triangle count t_e (left by the
+      // scatter launches, reset here): the same four terms as kJobEdgeTri
+      nf = 4;
+      for (int64_t e = t0 + lane_id(); e < t1; e += 64) {
+        const uint64_t te = J.tri[e];
+        if (te) J.tri[e] = 0u;
+        const int32_t u = J.task_src[e], v = col[e];
+        const uint64_t du = (uint64_t)(J.deg_rp[u + 1] - J.deg_rp[u]);
+        const uint64_t dv = (uint64_t)(J.deg_rp[v + 1] - J.deg_rp[v]);
+        acc[0] += te;
+        acc[1] += te * (te - (te ? 1 : 0)) / 2;
+        acc[2] += te * (du + dv - 4);
+        acc[3] += (du - 1) * (dv - 1);
+      }
     } else if ((KINDS & kKindVertexDeg) && kind == kJobVertexDeg) {
       // f0 += C(d, 2), f1 += C(d, 3) over the chunk's vertices
       nf = 2;
@@ -1476,7 +1523,7 @@ gpm_lgs_block(KernelArgs a) {
       // the edge-sorting area follows the largest tile of the launch
       acc[0] += clique_lgs_block<CE>(J.rp, J.col, J.k, u, d, part, parts, J.ordered != 0,
                                      blk_lds, scan_tmp, &row_next,
-                                     blk_lds + a.lds_words - kBlockWaves * kSortWords, ec);
+                                     blk_lds + a.lds_words - kBlockWaves * kSortWords, J.tri, ec);
       __syncthreads();  // the next root reuses the local graph's LDS
     }
   }
@@ -1519,6 +1566,7 @@ static hipError_t launch_kinds(uint32_t kinds, const KernelArgs& a, int blocks, 
     case kKindVertexDeg: return launch_t<kKindVertexDeg, CE>(a, blocks, lds, s);
     case kKindCliqueLgs: return launch_t<kKindCliqueLgs, CE>(a, blocks, lds, s);
     case kKindCycleWedge: return launch_t<kKindCycleWedge, CE>(a, blocks, lds, s);
+    case kKindEdgeTerms: return launch_t<kKindEdgeTerms, CE>(a, blocks, lds, s);
     case kKindCliqueLgs | kKindClique:
       return launch_t<kKindCliqueLgs | kKindClique, CE>(a, blocks, lds, s);
     default: return launch_t<kKindAll, CE>(a, blocks, lds, s);

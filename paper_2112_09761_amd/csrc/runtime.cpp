@@ -117,6 +117,8 @@ struct Slot {
   int32_t* d_fbuf = nullptr; size_t d_fbuf_bytes = 0;
   unsigned int* d_zero = nullptr; size_t d_zero_bytes = 0;  // wedge counters
   bool zero_dirty = true;
+  unsigned int* d_tri = nullptr; size_t d_tri_bytes = 0;    // per-edge triangle counters
+  bool tri_dirty = true;
   void* h_stage = nullptr; size_t h_stage_bytes = 0;    // pinned
   unsigned long long* h_res = nullptr; size_t h_res_words = 0;  // pinned
   bool busy = false;
@@ -154,6 +156,7 @@ struct gpm_ctx {
   int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
   int64_t opt_decompose = 1;                    // counting-only decomposition of named motifs
   int64_t opt_wedge_list = 1 << 19;             // distinct-endpoint list per 4-cycle wave
+  int64_t opt_edge_terms = 0;                   // 0 auto (triangle scatter), 1 per-edge intersection
   int lds_block_max = 65536;                    // dynamic LDS per workgroup (bytes)
   int64_t opt_tune_min_ms = 20;
   int64_t opt_wedge_mem = int64_t(16) << 30;   // cap of the 4-cycle counter arrays
@@ -544,6 +547,7 @@ struct JobPlanSet {
   std::vector<Job> jobs;
   std::vector<Plan> plans;
   std::vector<int64_t> need_words;  // per job: HBM frontier words per wave
+  int32_t next_tri_group = 1;       // triangle-scatter groups (Job::tri_group)
 };
 
 static int default_chunk(const gpm_ctx* c, int kind) {
@@ -592,6 +596,66 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
                                  JobPlanSet& js, QueryWork& qw);
 static void named(const char* name, gpm_pattern* p);
 
+// The per-edge motif terms (Σt_e, ΣC(t_e,2), Σt_e(d_u+d_v−4), Σ(d_u−1)(d_v−1))
+// as one job whose four result fields hold them (the query's next slot);
+// returns through *added the number of jobs appended.  Default: the k = 3
+// local-graph search scatters every triangle onto its three edges' counters
+// and a kJobEdgeTerms job folds them; when a root is too large for the
+// local-graph kernels, the counters would take more than a quarter of the
+// memory budget, or with edge_terms = 1: one intersection per edge.
+static gpm_status add_edge_term_jobs(gpm_ctx* c, Graph& g, JobPlanSet& js, int* added) {
+  gpm_status st = ensure_lower(c, g);
+  if (st) return st;
+  bool scatter = c->opt_edge_terms == 0 && !g.dag_only && c->opt_clique_lds &&
+                 c->opt_clique_algo != 1;
+  if (scatter) {
+    st = ensure_dag(c, g);
+    if (st) return st;
+    st = ensure_lgs(c, g, c->opt_lgs_max);
+    if (st) return st;
+    st = ensure_ren(c, g);
+    if (st) return st;
+    // the counters (4 B per edge) may take a quarter of the memory budget;
+    // beyond that the intersections, which need no memory of their own
+    scatter = g.n_big == 0 && g.dag_ordered && (size_t)g.dag.nnz * 4 <= c->budget / 4;
+  }
+  if (!scatter) {
+    Job J{};
+    J.kind = kJobEdgeTri;
+    J.rp = g.sym.rp;
+    J.col = g.sym.col;
+    J.task_src = g.lo_src;
+    J.task_dst = g.lo_dst;
+    J.n_tasks = g.n_lo;
+    J.chunk = default_chunk(c, kJobEdgeTri);
+    js.jobs.push_back(J);
+    js.need_words.push_back(0);
+    *added = 1;
+    return GPM_OK;
+  }
+  const int32_t grp = js.next_tri_group++;
+  Job E{};
+  E.kind = kJobEdgeTerms;
+  E.rp = g.dag.rp;
+  E.col = g.dag.col;
+  E.task_src = g.dag.src;
+  E.n_tasks = g.dag.nnz;
+  E.chunk = 4096;
+  E.tri_group = grp;
+  E.deg_rp = g.ren.rp;
+  js.jobs.push_back(E);
+  js.need_words.push_back(0);
+  const size_t before = js.jobs.size();
+  gpm_pattern p;
+  QueryWork tmp;
+  gpm_pattern_clique(3, &p);
+  st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
+  if (st) return st;
+  for (size_t i = before; i < js.jobs.size(); ++i) js.jobs[i].tri_group = grp;
+  *added = 1 + (int)(js.jobs.size() - before);
+  return GPM_OK;
+}
+
 // Jobs of a decomposed count: the degree terms (ΣC(d,2), ΣC(d,3)), the edge
 // terms (Σt_e, ΣC(t_e,2), Σt_e(d_u+d_v−4), Σ(d_u−1)(d_v−1)) and, for the
 // vertex-induced counts, the 4-clique (triangle for the wedge) and 4-cycle
@@ -620,17 +684,11 @@ static gpm_status add_decomposed_jobs(gpm_ctx* c, Graph& g, int dec, int mode, J
     js.need_words.push_back(0);
   }
   if (need_edge) {
-    Job J{};
-    J.kind = kJobEdgeTri;
-    J.rp = g.sym.rp;
-    J.col = g.sym.col;
-    J.task_src = g.lo_src;
-    J.task_dst = g.lo_dst;
-    J.n_tasks = g.n_lo;
-    J.chunk = default_chunk(c, kJobEdgeTri);
-    qw.edge_slot = qw.n_jobs++;
-    js.jobs.push_back(J);
-    js.need_words.push_back(0);
+    int added = 0;
+    qw.edge_slot = qw.n_jobs;
+    gpm_status st = add_edge_term_jobs(c, g, js, &added);
+    if (st) return st;
+    qw.n_jobs += added;
   }
   if (vi) {
     gpm_pattern p;
@@ -924,21 +982,12 @@ static gpm_status add_motif_jobs(gpm_ctx* c, Graph& g, int k, JobPlanSet& js, Qu
     qw.n_jobs += tmp.n_jobs;
     return GPM_OK;
   }
-  st = ensure_lower(c, g);
-  if (st) return st;
   {
-    Job J{};
-    J.kind = kJobEdgeTri;
-    J.rp = g.sym.rp;
-    J.col = g.sym.col;
-    J.task_src = g.lo_src;
-    J.task_dst = g.lo_dst;
-    J.n_tasks = g.n_lo;
-    J.chunk = default_chunk(c, kJobEdgeTri);
-    js.jobs.push_back(J);
-    js.need_words.push_back(0);
+    int added = 0;  // slot 1: the edge terms (first job appended)
+    st = add_edge_term_jobs(c, g, js, &added);
+    if (st) return st;
+    qw.n_jobs += added;
   }
-  qw.n_jobs += 1;
   if (k == 4) {
     gpm_pattern p;
     QueryWork tmp;
@@ -1051,6 +1100,7 @@ static void slot_free(Slot& s) {
   dev_free(s.d_res);
   dev_free(s.d_fbuf);
   dev_free(s.d_zero);
+  dev_free(s.d_tri);
   if (s.h_stage) (void)hipHostFree(s.h_stage);
   if (s.h_res) (void)hipHostFree(s.h_res);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
@@ -1102,18 +1152,25 @@ static std::vector<LaunchPlan> plan_launches(JobPlanSet& js, std::vector<int>& p
   const int nj = (int)js.jobs.size();
   perm.resize(nj);
   for (int i = 0; i < nj; ++i) perm[i] = i;
-  // workgroup jobs run in a kernel of their own, even without fission
-  auto own = [&](int i) { return js.jobs[i].kind == kJobCliqueLgsBlock; };
+  // launches run in phases: workgroup jobs first (a kernel of their own), then
+  // the per-wave kinds, then the edge-term jobs, which read what the triangle
+  // scatter of the earlier phases left (kernel boundaries order them)
+  auto phase = [&](int i) {
+    const int k = js.jobs[i].kind;
+    return k == kJobCliqueLgsBlock ? 0 : k == kJobEdgeTerms ? 2 : 1;
+  };
   std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-    if (own(a) != own(b)) return own(a);
+    if (phase(a) != phase(b)) return phase(a) < phase(b);
     return fission && js.jobs[a].kind < js.jobs[b].kind;
   });
   std::vector<LaunchPlan> out;
+  int last_phase = -1;
   for (int i = 0; i < nj; ++i) {
     const Job& J = js.jobs[perm[i]];
     uint32_t kb = 1u << J.kind;
-    if (out.empty() || ((fission || own(perm[i]) || out.back().kinds == kKindCliqueLgsBlock) &&
-                        out.back().kinds != kb)) {
+    const int ph = phase(perm[i]);
+    if (out.empty() || ph != last_phase || (fission && out.back().kinds != kb)) {
+      last_phase = ph;
       LaunchPlan L;
       L.first = i;
       L.kinds = kb;
@@ -1233,10 +1290,12 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   }
   const size_t zbytes = (size_t)waves * (size_t)zstride * 4;
   if (zbytes) {
-    void* before = s.d_zero;
+    // a reallocation may return the same address with new, uncleared memory
+    // beyond the old size: any change of capacity needs the fill
+    const size_t cap_before = s.d_zero_bytes;
     st = grow_dev(c, (void**)&s.d_zero, &s.d_zero_bytes, zbytes);
     if (st) return st;
-    if (before != (void*)s.d_zero) s.zero_dirty = true;
+    if (s.d_zero_bytes != cap_before) s.zero_dirty = true;
     if (s.zero_dirty) {
       if (launch_fill_u64((unsigned long long*)s.d_zero, (int64_t)(s.d_zero_bytes / 8), 0ull,
                           s.stream))
@@ -1244,7 +1303,37 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     }
     s.zero_dirty = true;  // until this group completes (every task restores zeros)
   }
-  *frontier_used = fbytes + zbytes;
+  // per-edge triangle counters: one region per scatter group (its DAG edge
+  // count, from the group's edge-term job), zero between launches
+  std::map<int32_t, int64_t> tri_off;
+  int64_t tri_words = 0;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].kind == kJobEdgeTerms) {
+      tri_off[jobs[i].tri_group] = tri_words;
+      tri_words += (int64_t)align_up((size_t)std::max<int64_t>(jobs[i].n_tasks, 1), 64);
+    }
+  const size_t tbytes = (size_t)tri_words * 4;
+  if (tbytes) {
+    if (fbytes + zbytes + tbytes > frontier_budget)
+      return fail(c, GPM_E_NOMEM, "per-edge triangle counters do not fit the memory budget");
+    const size_t cap_before = s.d_tri_bytes;  // (as for the wedge counters above)
+    st = grow_dev(c, (void**)&s.d_tri, &s.d_tri_bytes, tbytes);
+    if (st) return st;
+    if (s.d_tri_bytes != cap_before) s.tri_dirty = true;
+    if (s.tri_dirty) {
+      if (launch_fill_u64((unsigned long long*)s.d_tri, (int64_t)(s.d_tri_bytes / 8), 0ull,
+                          s.stream))
+        return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+    }
+    s.tri_dirty = true;  // until this group completes (the edge-term jobs restore zeros)
+    for (int i = 0; i < nj; ++i)
+      if (jobs[i].tri_group > 0) {
+        auto it = tri_off.find(jobs[i].tri_group);
+        if (it == tri_off.end()) return fail(c, GPM_E_DEVICE, "triangle scatter without edge terms");
+        jobs[i].tri = s.d_tri + it->second;
+      }
+  }
+  *frontier_used = fbytes + zbytes + tbytes;
 
   const size_t lds_bytes = (size_t)lds_words * 4 * kWavesPerBlock;
 
@@ -1363,6 +1452,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
 static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
   HIP_TRY(c, hipStreamSynchronize(s.stream));
   s.zero_dirty = false;
+  s.tri_dirty = false;
   float ms = 0.f;
   if (s.n_launch > 0) HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
   c->stats.kernel_ms = ms;
@@ -1505,6 +1595,7 @@ static gpm_status progress(gpm_ctx* c) {
     s.qkeys.clear();
     s.busy = false;
     s.zero_dirty = false;
+  s.tri_dirty = false;
     c->serve_frontier_in_use -= s.frontier_bytes_in_use;
     s.frontier_bytes_in_use = 0;
   }
@@ -1715,6 +1806,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
   else if (k == "lgs_block") c->opt_lgs_block = v != 0;
   else if (k == "decompose") c->opt_decompose = v != 0;
+  else if (k == "edge_terms") { if (v < 0 || v > 1) return fail(c, GPM_E_INVAL, "edge_terms 0..1"); c->opt_edge_terms = v; }
   else if (k == "wedge_list") { if (v < 64 || v > (1 << 24)) return fail(c, GPM_E_INVAL, "wedge_list 64..2^24"); c->opt_wedge_list = v; }
   else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }

@@ -164,7 +164,8 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                           ("granularity", [1]), ("clique_algo", [1, 2]),
                           ("lgs_tile", [64, 256]), ("lgs_max", [64, 100]),
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
-                          ("rename", [0]), ("cycle4_algo", [1, 2]), ("decompose", [0])]:
+                          ("rename", [0]), ("cycle4_algo", [1, 2]), ("decompose", [0]),
+                          ("edge_terms", [1])]:
             for v in vals:
                 ctx.set_option(opt, v)
                 for n, e in exp.items():
@@ -174,7 +175,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                                  "clique_lds": 1, "granularity": 0, "clique_algo": 0,
                                  "lgs_tile": 128, "lgs_max": 2048, "lgs_split": 1,
                                  "leaf_cap": 128, "rename": 1, "cycle4_algo": 0,
-                                 "decompose": 1}[opt])
+                                 "decompose": 1, "edge_terms": 0}[opt])
     finally:
         ctx.unload(gid)
 
@@ -423,6 +424,38 @@ def test_serving_alone_vs_mix(ctx, oracle):
             assert x == oracle.count(gs[a], p, False)
         assert ctx.inflight() == 0
     finally:
+        for gid in ids:
+            ctx.unload(gid)
+
+
+def test_serving_counter_buffers_grow(ctx, oracle):
+    """One serving slot whose zero-initialised counter buffers (4-cycle
+    wedges, per-edge triangles) must grow from group to group: a grown buffer
+    may come back at the same address with uncleared memory beyond its old
+    size, which must be cleared before use."""
+    from paper_2112_09761_amd import gpm
+    gs = [synth.rmat(8, 8, seed=1501), synth.rmat(11, 12, seed=1502),
+          synth.rmat(13, 12, seed=1503)]
+    ids = [ctx.load(g) for g in gs]
+    kinds = [("cycle4", E), ("diamond", E), ("tailed_triangle", V), ("path4", V)]
+    exp = {(i, p, m): oracle.count(g, p, m == V) for i, g in enumerate(gs) for p, m in kinds}
+    exp_m4 = [oracle.motifs4(g) for g in gs]
+    try:
+        ctx.set_option("serve_slots", 1)
+        for upto in (1, 2, 3, 2, 3):
+            tickets = []
+            for i in range(upto):
+                for p, m in kinds:
+                    tickets.append(((i, p, m), ctx.submit(gpm.count_query(ids[i], p, m))))
+                tickets.append((("m4", i), ctx.submit(gpm.motif_query(ids[i], 4))))
+            for key, t in tickets:
+                got = ctx.wait(t)
+                if key[0] == "m4":
+                    assert got == exp_m4[key[1]], (upto, key)
+                else:
+                    assert got[0] == exp[key], (upto, key)
+    finally:
+        ctx.set_option("serve_slots", 4)
         for gid in ids:
             ctx.unload(gid)
 
