@@ -269,8 +269,6 @@ __device__ __forceinline__ uint64_t clique_edge(const int64_t* __restrict__ rp,
 // ANDed rows.  One wave per root vertex.
 // ---------------------------------------------------------------------------
 
-constexpr int kLgsMaxWords = kLgsMaxVertices / 64;  // words per bitmap row
-
 // position of the r-th (0-based) set bit of x (r < popcount(x))
 __device__ __forceinline__ int select64(uint64_t x, int r) {
   int pos = 0;

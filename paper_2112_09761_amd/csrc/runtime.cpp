@@ -1836,7 +1836,6 @@ gpm_status gpm_load_csr(gpm_ctx* c, int64_t n, int64_t nnz, const int64_t* row_p
   if (n < 0 || nnz < 0 || n >= (int64_t)INT32_MAX) return fail(c, GPM_E_INVAL, "bad n or nnz");
   if (!row_ptr || (nnz > 0 && !col)) return fail(c, GPM_E_INVAL, "null CSR array");
   const bool dag = (flags & GPM_CSR_DAG) != 0;
-  const bool sym = (flags & GPM_CSR_SYMMETRIC) != 0 || !dag;
   if (dag && (flags & GPM_CSR_SYMMETRIC)) return fail(c, GPM_E_INVAL, "SYMMETRIC and DAG both set");
   HIP_TRY(c, hipSetDevice(c->device));
   auto g = std::make_unique<Graph>();

@@ -460,6 +460,29 @@ def test_serving_counter_buffers_grow(ctx, oracle):
             ctx.unload(gid)
 
 
+def test_edge_terms_fallback_with_large_roots(ctx, oracle):
+    """Per-edge motif terms: with roots beyond the local-graph limit the
+    triangle scatter cannot see every triangle, so the per-edge intersections
+    run instead; both routes must give the closed forms and the oracle."""
+    import math
+    kn = synth.complete(100)
+    g = synth.rmat(13, 16, seed=1301)   # 245 roots with more than 64 out-neighbours
+    ids = [ctx.load(kn), ctx.load(g)]
+    c4 = math.comb(100, 4)
+    try:
+        for lim in (64, 2048):
+            ctx.set_option("lgs_max", lim)
+            assert ctx.motifs(ids[0], 4) == [0, 0, 0, 0, 0, c4], lim
+            assert ctx.count(ids[0], "diamond", E) == 6 * c4, lim
+            assert ctx.count(ids[0], "tailed_triangle", E) == 12 * c4, lim
+            assert ctx.motifs(ids[1], 4) == oracle.motifs4(g), lim
+            assert ctx.count(ids[1], "path4", V) == oracle.count(g, "path4", True), lim
+    finally:
+        ctx.set_option("lgs_max", 2048)
+        for gid in ids:
+            ctx.unload(gid)
+
+
 def test_error_paths_on_device(ctx, oracle):
     """Load-time validation, unknown ids, bad modes, unsupported patterns on a
     DAG-only graph, a memory budget too small for any frontier, and a full
