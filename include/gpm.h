@@ -182,7 +182,8 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     second pass (64..2^24, default 2^19); a task with more
  *                     walks its wedges twice instead (identical counts)
  *   "budget"          device memory budget in bytes (as in gpm_create)
- *   "max_batch", "serve_slots", "max_pending"   serving limits
+ *   "max_batch", "serve_slots", "max_pending", "serve_light_ms"   serving
+ *                     limits (see gpm_submit)
  *   "tune_min_ms"     autotuner threshold (see "autotune")
  *   "count_elements"  1 = instrumented kernels count intersected elements
  *                     (slower; never used for timing)
@@ -322,10 +323,13 @@ gpm_status gpm_count_batch(gpm_ctx *ctx, int32_t nq, const gpm_query *queries,
                            uint64_t *outs);
 
 /* Serving: submit one query without blocking.  The query is admitted when a
- * launch slot is free and its frontier memory fits the budget; queries
- * admitted together share one persistent launch, and launches on different
- * slots overlap on the device.  GPM_E_BUSY when the pending list is full.
- * *ticket_out identifies the query for gpm_poll / gpm_wait. */
+ * launch slot is free and its frontier memory fits the budget; launches on
+ * different slots overlap on the device.  Queries whose last run alone took
+ * at most "serve_light_ms" (default 50) are light: light queries admitted
+ * together share one persistent launch (at most "max_batch").  Other queries
+ * (heavy, or not yet measured) run alone and hold at most half of the slots,
+ * so light queries keep slots of their own.  GPM_E_BUSY when the pending list
+ * is full.  *ticket_out identifies the query for gpm_poll / gpm_wait. */
 gpm_status gpm_submit(gpm_ctx *ctx, const gpm_query *query, int64_t *ticket_out);
 
 /* Progress the serving loop; *done_out = 1 when the ticket's result is

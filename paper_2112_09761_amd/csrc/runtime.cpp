@@ -122,6 +122,7 @@ struct Slot {
   void* h_stage = nullptr; size_t h_stage_bytes = 0;    // pinned
   unsigned long long* h_res = nullptr; size_t h_res_words = 0;  // pinned
   bool busy = false;
+  bool heavy = false;      // serving: the running group is a heavy or unknown query
   size_t frontier_bytes_in_use = 0;
   std::vector<QueryWork> queries;
   std::vector<std::string> qkeys;  // serving: cost keys of the launch's queries
@@ -1594,8 +1595,9 @@ static gpm_status progress(gpm_ctx* c) {
     s.queries.clear();
     s.qkeys.clear();
     s.busy = false;
+    s.heavy = false;
     s.zero_dirty = false;
-  s.tri_dirty = false;
+    s.tri_dirty = false;
     c->serve_frontier_in_use -= s.frontier_bytes_in_use;
     s.frontier_bytes_in_use = 0;
   }
@@ -1603,6 +1605,12 @@ static gpm_status progress(gpm_ctx* c) {
     auto it = c->qcost.find(query_key(q));
     return it != c->qcost.end() && it->second <= (double)c->opt_serve_light_ms;
   };
+  // heavy (or not yet measured) queries run alone and may hold at most half
+  // of the slots, so light queries keep slots of their own
+  int heavy_busy = 0;
+  for (int i = 1; i <= ns; ++i)
+    if (c->slots[i].busy && c->slots[i].heavy) ++heavy_busy;
+  const int heavy_max = std::max(1, ns / 2);
   for (int i = 1; i <= ns && !c->pending.empty(); ++i) {
     Slot& s = c->slots[i];
     if (s.busy) continue;
@@ -1612,8 +1620,13 @@ static gpm_status progress(gpm_ctx* c) {
     JobPlanSet js;
     std::vector<QueryWork> qs;
     std::vector<std::string> keys;
-    const bool batchable = light(c->pending.front().q);
-    for (auto it = c->pending.begin(); it != c->pending.end() && (int64_t)qs.size() < c->opt_max_batch;) {
+    // the group starts at the first pending query this slot may take
+    auto first = c->pending.begin();
+    if (heavy_busy >= heavy_max)
+      while (first != c->pending.end() && !light(first->q)) ++first;
+    if (first == c->pending.end()) continue;  // only heavy work waits: keep the slot for light
+    const bool batchable = light(first->q);
+    for (auto it = first; it != c->pending.end() && (int64_t)qs.size() < c->opt_max_batch;) {
       if (!qs.empty() && (!batchable || !light(it->q))) {
         ++it;
         continue;
@@ -1666,6 +1679,8 @@ static gpm_status progress(gpm_ctx* c) {
     s.queries = qs;
     s.qkeys = keys;
     s.busy = true;
+    s.heavy = !batchable;
+    if (s.heavy) ++heavy_busy;
     s.frontier_bytes_in_use = used;
     c->serve_frontier_in_use += used;
   }
