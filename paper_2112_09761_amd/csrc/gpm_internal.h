@@ -54,6 +54,8 @@ enum JobKind : int32_t {
   kJobCliqueLgsBlock = 7,  // k-clique (k = 3..5): the local graph of one large
                            // root shared by a whole workgroup (own kernel)
   kJobEdgeTerms = 8,   // per-edge motif terms from per-edge triangle counts
+  kJobTriScatter = 9,  // triangles by local graph search (one wave per root),
+                       // each added to its three edges' counters
 };
 
 constexpr uint32_t kKindClique = 1u << kJobClique;
@@ -64,9 +66,11 @@ constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
 constexpr uint32_t kKindCycleWedge = 1u << kJobCycleWedge;
 constexpr uint32_t kKindCliqueLgsBlock = 1u << kJobCliqueLgsBlock;
 constexpr uint32_t kKindEdgeTerms = 1u << kJobEdgeTerms;
+constexpr uint32_t kKindTriScatter = 1u << kJobTriScatter;
 // kinds of the per-wave persistent kernel (the workgroup kernel has its own)
 constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg |
-                              kKindCliqueLgs | kKindCycleWedge | kKindEdgeTerms;
+                              kKindCliqueLgs | kKindCycleWedge | kKindEdgeTerms |
+                              kKindTriScatter;
 constexpr int kLgsMaxVertices = 2048;   // local graphs handled by the bitmap kernel
 constexpr int kBlockWaves = 16;         // workgroup of the large-root kernel (1024 threads)
 constexpr int kLgsBlockMaxVertices = kBlockWaves * 64;  // one vertex per thread in its scans

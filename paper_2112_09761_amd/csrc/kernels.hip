@@ -565,7 +565,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
   return c;
 }
 
-template <bool CE, typename TL, typename TP, typename TH, typename TR>
+template <bool CE, bool SC, typename TL, typename TP, typename TH, typename TR>
 __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ col, int k,
                                                int32_t u, int32_t d, int32_t part,
@@ -590,16 +590,19 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   // k = 3: every hit is a triangle at this root
   if (k == 3) {
     if (part != 0) return 0;
-    if (!tri) return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
-    // triangle scatter: P holds the per-row counters (edges u-L[i])
-    for (int32_t i = l; i < d; i += 64) P[i] = 0;
-    wave_sync_mem();
-    lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr, P, tri);
-    wave_sync_mem();
-    const int64_t e0 = rp[u];
-    for (int32_t i = l; i < d; i += 64)
-      if (P[i]) atomicAdd(&tri[e0 + i], (unsigned int)P[i]);
-    return 0;
+    if constexpr (!SC) {
+      return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
+    } else {
+      // triangle scatter: P holds the per-row counters (edges u-L[i])
+      for (int32_t i = l; i < d; i += 64) P[i] = 0;
+      wave_sync_mem();
+      lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr, P, tri);
+      wave_sync_mem();
+      const int64_t e0 = rp[u];
+      for (int32_t i = l; i < d; i += 64)
+        if (P[i]) atomicAdd(&tri[e0 + i], (unsigned int)P[i]);
+      return 0;
+    }
   }
   lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
   wave_sync_mem();
@@ -1250,6 +1253,43 @@ __device__ __forceinline__ void flush(unsigned long long* results, int slot, uin
   }
 }
 
+// Root tasks [t0, t1) of a local-graph clique job, one wave per root; the
+// tile is the wave's LDS area when the root fits it, else its HBM region.
+template <bool CE, bool SC>
+__device__ __forceinline__ void lgs_tasks(const Job& J, const KernelArgs& a, int32_t* my,
+                                          int32_t* fb, int64_t t0, int64_t t1, uint64_t* acc,
+                                          ElemCounter& ec) {
+  const int64_t* __restrict__ rp = J.rp;
+  const int32_t* __restrict__ col = J.col;
+  const int k = J.k;
+  for (int64_t t = t0; t < t1; ++t) {
+    int32_t u = uni(J.task_src[t]);
+    int32_t d = uni((int32_t)(rp[u + 1] - rp[u]));
+    int32_t part = 0, parts = 1;
+    if (J.task_dst) {  // split root: (part, parts) packed as part | parts << 16
+      int32_t enc = uni(J.task_dst[t]);
+      part = enc & 0xffff;
+      parts = enc >> 16;
+    }
+    // tile layout (lgs_tile_words): L | P | H | R
+    if (d <= a.lgs_tile) {
+      int32_t* L = my;
+      int32_t* Pp = L + a.lgs_tile;
+      unsigned long long* H = (unsigned long long*)(my + lgs_hash_offset(a.lgs_tile));
+      unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
+      acc[0] += clique_lgs<CE, SC>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
+                                   J.tri, ec);
+    } else {
+      int32_t* L = fb;
+      int32_t* Pp = fb + J.cap;
+      unsigned long long* H = (unsigned long long*)(fb + lgs_hash_offset(J.cap));
+      unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
+      acc[0] += clique_lgs<CE, SC>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
+                                   J.tri, ec);
+    }
+  }
+}
+
 template <uint32_t KINDS, bool CE>
 __global__ void __launch_bounds__(kWavesPerBlock * 64)
 gpm_persistent(KernelArgs a) {
@@ -1316,34 +1356,17 @@ gpm_persistent(KernelArgs a) {
           acc[0] += clique_edge<CE>(rp, col, k, U, du, v, bufs, P, J.cap, st_words, ec);
         }
       }
-    } else if ((KINDS & kKindCliqueLgs) && kind == kJobCliqueLgs) {
+    } else if (((KINDS & kKindCliqueLgs) && kind == kJobCliqueLgs) ||
+               ((KINDS & kKindTriScatter) && kind == kJobTriScatter)) {
       nf = 1;
-      const int k = J.k;
-      for (int64_t t = t0; t < t1; ++t) {
-        int32_t u = uni(J.task_src[t]);
-        int32_t d = uni((int32_t)(rp[u + 1] - rp[u]));
-        int32_t part = 0, parts = 1;
-        if (J.task_dst) {  // split root: (part, parts) packed as part | parts << 16
-          int32_t enc = uni(J.task_dst[t]);
-          part = enc & 0xffff;
-          parts = enc >> 16;
-        }
-        // tile layout (lgs_tile_words): L | P | H | R
-        if (d <= a.lgs_tile) {
-          int32_t* L = my;
-          int32_t* Pp = L + a.lgs_tile;
-          unsigned long long* H = (unsigned long long*)(my + lgs_hash_offset(a.lgs_tile));
-          unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
-                                   J.tri, ec);
-        } else {
-          int32_t* L = fb;
-          int32_t* Pp = fb + J.cap;
-          unsigned long long* H = (unsigned long long*)(fb + lgs_hash_offset(J.cap));
-          unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
-          acc[0] += clique_lgs<CE>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
-                                   J.tri, ec);
-        }
+      // the scatter variant is compiled only into instances that take it
+      if constexpr ((KINDS & kKindTriScatter) != 0) {
+        if (kind == kJobTriScatter)
+          lgs_tasks<CE, true>(J, a, my, fb, t0, t1, acc, ec);
+        else
+          lgs_tasks<CE, false>(J, a, my, fb, t0, t1, acc, ec);
+      } else {
+        lgs_tasks<CE, false>(J, a, my, fb, t0, t1, acc, ec);
       }
     } else if ((KINDS & kKindCycleWedge) && kind == kJobCycleWedge) {
       nf = 1;
@@ -1565,6 +1588,7 @@ static hipError_t launch_kinds(uint32_t kinds, const KernelArgs& a, int blocks, 
     case kKindCliqueLgs: return launch_t<kKindCliqueLgs, CE>(a, blocks, lds, s);
     case kKindCycleWedge: return launch_t<kKindCycleWedge, CE>(a, blocks, lds, s);
     case kKindEdgeTerms: return launch_t<kKindEdgeTerms, CE>(a, blocks, lds, s);
+    case kKindTriScatter: return launch_t<kKindTriScatter, CE>(a, blocks, lds, s);
     case kKindCliqueLgs | kKindClique:
       return launch_t<kKindCliqueLgs | kKindClique, CE>(a, blocks, lds, s);
     default: return launch_t<kKindAll, CE>(a, blocks, lds, s);

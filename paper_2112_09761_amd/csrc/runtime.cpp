@@ -652,7 +652,12 @@ static gpm_status add_edge_term_jobs(gpm_ctx* c, Graph& g, JobPlanSet& js, int* 
   gpm_pattern_clique(3, &p);
   st = add_count_jobs(c, g, p, GPM_EDGE_INDUCED, js, tmp);
   if (st) return st;
-  for (size_t i = before; i < js.jobs.size(); ++i) js.jobs[i].tri_group = grp;
+  for (size_t i = before; i < js.jobs.size(); ++i) {
+    js.jobs[i].tri_group = grp;
+    // one-wave roots get their own kind, so that the clique kernels do not
+    // carry the scatter code (the workgroup kernel branches on the group)
+    if (js.jobs[i].kind == kJobCliqueLgs) js.jobs[i].kind = kJobTriScatter;
+  }
   *added = 1 + (int)(js.jobs.size() - before);
   return GPM_OK;
 }
@@ -1230,7 +1235,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   // their local graph in the wave's HBM region
   int32_t lgs_T = 0;
   for (int i = 0; i < nj; ++i)
-    if (jobs[i].kind == kJobCliqueLgs) {
+    if (jobs[i].kind == kJobCliqueLgs || jobs[i].kind == kJobTriScatter) {
       lgs_T = (int32_t)c->opt_lgs_tile;
       if (jobs[i].cap > lgs_T) need[i] = std::max<int64_t>(need[i], lgs_tile_words(jobs[i].cap));
     }
@@ -1253,6 +1258,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   bool lgs_only = nj > 0;
   for (int i = 0; i < nj; ++i)
     if (jobs[i].kind != kJobCliqueLgs && jobs[i].kind != kJobCliqueLgsBlock &&
+        jobs[i].kind != kJobTriScatter &&
         jobs[i].kind != kJobClique)
       lgs_only = false;
   const int64_t wpc = c->opt_waves_per_cu > 0 ? c->opt_waves_per_cu : (lgs_only ? 24 : 16);
@@ -1411,7 +1417,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     a.counters = s.d_res + res_words + q_words + 4 * i;
     a.fbuf = fbytes ? s.d_fbuf : nullptr;
     a.wave_stride = stride;
-    const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs)) != 0;
+    const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs | kKindTriScatter)) != 0;
     a.lds_words = uses_lds ? lds_words : 0;
     a.lgs_tile = lgs_T;
     a.zbuf = (L.kinds & kKindCycleWedge) ? s.d_zero : nullptr;
