@@ -20,6 +20,9 @@
  *                       subset, isomorphism by all k! bijections (tiny n);
  *   orc_count_embed     injective homomorphisms (plus non-edge preservation
  *                       in induced mode) divided by |Aut(P)|;
+ *   orc_list_embed      listing: the same embeddings, one emitted per
+ *                       distinct subgraph (the smallest of its automorphic
+ *                       images);
  *   orc_triangles       triangles with marker arrays on an oriented graph,
  *                       also per-vertex and per-edge triangle counts;
  *   orc_cliques         k-cliques by recursive marker-array enumeration on
@@ -107,6 +110,16 @@ static int next_perm(int *p, int k)
     return 1;
 }
 
+/* does the permutation p of the pattern vertices preserve adjacency? */
+static int is_automorphism(int k, int adj[MAXK][MAXK], const int *p)
+{
+    int ok = 1;
+    for (int i = 0; i < k && ok; i++)
+        for (int j = 0; j < k; j++)
+            if (adj[i][j] != adj[p[i]][p[j]]) { ok = 0; break; }
+    return ok;
+}
+
 /* |Aut(P)|: permutations of the pattern vertices preserving adjacency. */
 int orc_pattern_aut(int k, const int32_t *pe, int npe, uint64_t *aut_out)
 {
@@ -117,11 +130,7 @@ int orc_pattern_aut(int k, const int32_t *pe, int npe, uint64_t *aut_out)
     for (int i = 0; i < k; i++) p[i] = i;
     uint64_t cnt = 0;
     do {
-        int ok = 1;
-        for (int i = 0; i < k && ok; i++)
-            for (int j = 0; j < k; j++)
-                if (adj[i][j] != adj[p[i]][p[j]]) { ok = 0; break; }
-        cnt += ok;
+        cnt += is_automorphism(k, adj, p);
     } while (next_perm(p, k));
     *aut_out = cnt;
     return ORC_OK;
@@ -292,6 +301,116 @@ int orc_count_embed(int64_t n, const int64_t *rp, const int32_t *col,
     total /= aut;
     if (!fits64(total)) return ORC_EOVERFLOW;
     *out = (uint64_t)total;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* O1c: listing (Sec. 2.1: listing enumerates every match), serial.     */
+/* Every embedding is enumerated as in O1b; of the |Aut(P)| embeddings  */
+/* of one subgraph exactly one is emitted: the one whose tuple of       */
+/* images (indexed by pattern vertex) is lexicographically smallest     */
+/* among its compositions with the automorphisms.                       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    embed_plan pl;
+    int n_aut;
+    int aut[40320][MAXK];     /* all automorphisms (k! <= 40320)           */
+    int32_t *out;
+    int64_t cap;
+    u128 found;
+} list_ctx;
+
+/* is the match t (t[i] = image of pattern vertex i) the smallest of its
+ * automorphic images t o s? */
+static int smallest_image(const list_ctx *c, const int64_t *t)
+{
+    int k = c->pl.k;
+    for (int a = 0; a < c->n_aut; a++) {
+        const int *s = c->aut[a];
+        for (int i = 0; i < k; i++) {
+            if (t[s[i]] < t[i]) return 0;   /* t o s precedes t */
+            if (t[s[i]] > t[i]) break;
+        }
+    }
+    return 1;
+}
+
+static void list_rec(list_ctx *c, int depth, int64_t *img)
+{
+    const embed_plan *pl = &c->pl;
+    int k = pl->k;
+    if (depth == k) {
+        int64_t t[MAXK];
+        for (int d = 0; d < k; d++) t[pl->order[d]] = img[d];
+        if (!smallest_image(c, t)) return;
+        if ((u128)c->cap > c->found)
+            for (int i = 0; i < k; i++) c->out[(int64_t)c->found * k + i] = (int32_t)t[i];
+        c->found++;
+        return;
+    }
+    int64_t p = img[pl->parent[depth]];
+    for (int64_t e = pl->rp[p]; e < pl->rp[p + 1]; e++) {
+        int64_t x = pl->col[e];
+        int good = 1;
+        for (int d = 0; d < depth && good; d++) {
+            if (x == img[d]) good = 0;                       /* injective */
+            else if (pl->padj[depth][d]) good = has_edge(pl->rp, pl->col, x, img[d]);
+            else if (pl->induced) good = !has_edge(pl->rp, pl->col, x, img[d]);
+        }
+        if (!good) continue;
+        img[depth] = x;
+        list_rec(c, depth + 1, img);
+    }
+}
+
+/* Rows out[cap][k] (row r: the graph vertex of each pattern vertex) and the
+ * total number of matches in *count_out; rows past cap are counted only. */
+int orc_list_embed(int64_t n, const int64_t *rp, const int32_t *col,
+                   int k, const int32_t *pe, int npe, int induced,
+                   int32_t *out, int64_t cap, uint64_t *count_out)
+{
+    int adj[MAXK][MAXK];
+    int st = pattern_matrix(k, pe, npe, adj);
+    if (st) return st;
+    if (cap < 0 || (cap > 0 && !out)) return ORC_EINVAL;
+    list_ctx *c = (list_ctx *)calloc(1, sizeof(list_ctx));
+    if (!c) return ORC_ENOMEM;
+    c->out = out;
+    c->cap = cap;
+    int p[MAXK];
+    for (int i = 0; i < k; i++) p[i] = i;
+    do {
+        if (is_automorphism(k, adj, p)) memcpy(c->aut[c->n_aut++], p, sizeof p);
+    } while (next_perm(p, k));
+
+    embed_plan *pl = &c->pl;
+    pl->k = k; pl->induced = induced; pl->rp = rp; pl->col = col;
+    /* breadth-first order from pattern vertex 0, as in O1b */
+    int seen[MAXK] = {0}, head = 0, tail = 0;
+    pl->order[tail++] = 0; seen[0] = 1;
+    while (head < tail) {
+        int x = pl->order[head++];
+        for (int y = 0; y < k; y++)
+            if (adj[x][y] && !seen[y]) { seen[y] = 1; pl->order[tail++] = y; }
+    }
+    for (int d = 0; d < k; d++)
+        for (int e = 0; e < k; e++)
+            pl->padj[d][e] = adj[pl->order[d]][pl->order[e]];
+    pl->parent[0] = -1;
+    for (int d = 1; d < k; d++) {
+        pl->parent[d] = -1;
+        for (int e = 0; e < d; e++)
+            if (pl->padj[d][e]) { pl->parent[d] = e; break; }
+    }
+    int64_t img[MAXK];
+    for (int64_t v = 0; v < n; v++) {
+        img[0] = v;
+        list_rec(c, 1, img);
+    }
+    u128 found = c->found;
+    free(c);
+    if (!fits64(found)) return ORC_EOVERFLOW;
+    *count_out = (uint64_t)found;
     return ORC_OK;
 }
 

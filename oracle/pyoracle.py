@@ -63,6 +63,8 @@ def _declare(L):
         f = getattr(L, name)
         f.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int, P_I32,
                       ctypes.c_int, ctypes.c_int, P_U64]
+    L.orc_list_embed.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int, P_I32,
+                                 ctypes.c_int, ctypes.c_int, P_I32, ctypes.c_int64, P_U64]
     L.orc_triangles.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
                                 P_U64, P_U64, P_U64]
     L.orc_cliques.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
@@ -131,6 +133,21 @@ def count_embed(g, pattern, induced: bool) -> int:
     _check(lib().orc_count_embed(n, prp, pcol, k, pe.ctypes.data_as(P_I32),
                                  npe, int(induced), ctypes.byref(out)))
     return out.value
+
+
+def list_embed(g, pattern, induced: bool, cap: int | None = None):
+    """Listing: one row per distinct match, row[i] = graph vertex of pattern
+    vertex i, each the smallest of its automorphic images (serial; moderate
+    graphs).  Returns (rows[min(count, cap), k] int32, count)."""
+    n, rp, col, prp, pcol = _csr(g)
+    k, npe, pe = _pat(pattern)
+    if cap is None:
+        cap = count_embed(g, pattern, induced)
+    out = np.zeros((max(cap, 1), k), dtype=np.int32)
+    cnt = ctypes.c_uint64()
+    _check(lib().orc_list_embed(n, prp, pcol, k, pe.ctypes.data_as(P_I32), npe, int(induced),
+                                out.ctypes.data_as(P_I32), cap, ctypes.byref(cnt)))
+    return out[:min(cap, cnt.value)], cnt.value
 
 
 def triangles(g, order: int = 1, local: bool = False):

@@ -54,6 +54,13 @@ MUTATIONS = {
                        "if (adj[i][j] != adj[p[i]][j]) { ok = 0; break; }"),
     "triangle_marker_first": ("for (int64_t p = orp[a]; p < orp[a + 1]; p++) marker[ocol[p]] = p + 1;",
                               "for (int64_t p = orp[a] + 1; p < orp[a + 1]; p++) marker[ocol[p]] = p + 1;"),
+    "list_not_injective": ("if (x == img[d]) good = 0;", "if (0) good = 0;"),
+    "list_induced_ignored": ("else if (pl->induced) good = !has_edge(pl->rp, pl->col, x, img[d]);",
+                             "else if (0) good = !has_edge(pl->rp, pl->col, x, img[d]);"),
+    "list_every_embedding": ("if (!smallest_image(c, t)) return;", "if (0) return;"),
+    "list_image_compare": ("if (t[s[i]] > t[i]) break;", "if (t[s[i]] > t[i]) continue;"),
+    "list_row_columns": ("for (int d = 0; d < k; d++) t[pl->order[d]] = img[d];",
+                         "for (int d = 0; d < k; d++) t[d] = img[d];"),
     "has_edge_search": ("if (col[mid] < v) lo = mid + 1; else hi = mid;\n    }\n    return lo < rp[u + 1]",
                         "if (col[mid] <= v) lo = mid + 1; else hi = mid;\n    }\n    return lo < rp[u + 1]"),
 }
@@ -117,6 +124,19 @@ def battery():
                 check("nx embed mono " + name, O.count_embed(g, name, False), mono)
                 check("nx fast ind " + name, O.count(g, name, True), ind)
                 check("nx fast mono " + name, O.count(g, name, False), mono)
+                for induced, exp in ((True, ind), (False, mono)):
+                    rows, cnt = O.list_embed(g, name, induced, cap=exp + 8)
+                    check("list count " + name, cnt, exp)
+                    edges = O.PATTERNS[name][1]
+                    ok = all(len(set(r.tolist())) == len(r) and
+                             all(G.has_edge(int(r[a]), int(r[b])) for a, b in edges) and
+                             (not induced or
+                              G.subgraph([int(x) for x in r]).number_of_edges() == len(edges))
+                             for r in rows)
+                    check("list rows valid " + name, ok, True)
+                    sets = {frozenset(frozenset((int(r[a]), int(r[b]))) for a, b in edges)
+                            for r in rows}
+                    check("list rows distinct " + name, len(sets), len(rows))
         g = synth.erdos_renyi(300, 0.05, 950)
         A = np.zeros((g.n, g.n))
         A[np.repeat(np.arange(g.n), np.diff(g.row_ptr)), g.col] = 1
