@@ -302,6 +302,33 @@ gpm_status gpm_motifs(gpm_ctx *ctx, int32_t graph_id, int k,
                       uint64_t *counts_out, size_t len);
 
 /* ---------------------------------------------------------------------- */
+/* listing                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Subgraph listing (Sec. 2.1: listing enumerates every match, where
+ * counting only reports how many there are; the list() call of the paper's
+ * interface, Sec. 4).  Each distinct match of `pattern` in graph `graph_id`
+ * is written once, as a row of k int32 vertex ids in the caller's
+ * numbering: out[r*k + j] is the graph vertex matched to pattern vertex j.
+ * `out` is device memory on the context's device with room for `cap` rows
+ * (cap * k int32, caller-owned); it may be NULL when cap == 0.
+ * *count_out (host) receives the total number of matches, which equals
+ * gpm_count's.  Overflow: when *count_out > cap only cap rows were written
+ * (which ones is unspecified), and the caller can retry with a larger
+ * buffer.  Row order is unspecified.  Each row is one representative
+ * embedding of its subgraph: no two rows share a vertex set (cliques,
+ * vertex-induced mode) or an edge set (edge-induced mode).  Every pattern
+ * runs the plan-driven walk, never a counting-only shortcut: cliques on the
+ * degree-oriented DAG, other patterns on the symmetric graph.  Blocks until
+ * the rows and the count are complete.  Errors: GPM_E_INVAL (unknown graph,
+ * cap < 0, out NULL with cap > 0, bad mode), GPM_E_PATTERN,
+ * GPM_E_UNSUPPORTED (non-clique pattern on a DAG-only graph), GPM_E_NOMEM
+ * (frontier buffers), GPM_E_DEVICE; on error nothing is reported in
+ * *count_out and the contents of out are unspecified. */
+gpm_status gpm_list(gpm_ctx *ctx, int32_t graph_id, const gpm_pattern *pattern,
+                    int mode, int32_t *out, int64_t cap, uint64_t *count_out);
+
+/* ---------------------------------------------------------------------- */
 /* batched and served execution                                            */
 /* ---------------------------------------------------------------------- */
 

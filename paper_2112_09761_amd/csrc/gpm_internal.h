@@ -149,11 +149,34 @@ __host__ __device__ inline int64_t lgs_tile_words(int64_t T) {
 
 // The workgroup kernel lays out a root of d vertices as a tile with T = d.
 
+// One listing launch (Sec. 2.1: listing enumerates every match instead of
+// counting it): the plan-driven walk of one pattern over one graph view,
+// whose leaf depth writes each match as a row of k vertex ids.
+struct ListArgs {
+  Plan plan;
+  const int64_t* rp;         // graph view: CSR offsets
+  const int32_t* col;        //             CSR neighbours
+  const int32_t* task_src;   // root task t: the edge (task_src[t], task_dst[t]),
+  const int32_t* task_dst;   //   or the vertex t when task_src is null (k == 1)
+  int64_t n_tasks;
+  int32_t chunk;             // root tasks per queue pop
+  int32_t cap;               // frontier capacity (elements per stored depth)
+  int32_t k;
+  int8_t out_col[kMaxK];     // depth -> column of the row (the pattern vertex)
+  const int32_t* ids;        // view id -> caller's vertex id; null: identity
+  int32_t* out;              // rows [out_cap][k]
+  int64_t out_cap;
+  unsigned long long* cursor;  // [0]: next chunk, [1]: matches found (rows claimed)
+  int32_t* fbuf;             // frontier buffers: wave_stride words per wave
+  int64_t wave_stride;
+};
+
 // Host-side launchers (kernels.hip).  Return a hipError_t as int.
 int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a,
                       int blocks, size_t lds_bytes, void* stream);
 int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max_blocks,
                      size_t lds_bytes, void* stream);
+int launch_list(const ListArgs& a, int blocks, void* stream);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
 
 }  // namespace gpm

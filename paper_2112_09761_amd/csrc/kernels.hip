@@ -1215,6 +1215,171 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
+// listing (Sec. 2.1: every match is enumerated instead of counted)
+// ---------------------------------------------------------------------------
+
+// Claim rows for the lanes set in m (one atomic per wave) and return this
+// lane's row: the lanes' rows are consecutive in lane order.
+__device__ __forceinline__ int64_t claim_rows(unsigned long long* cursor, uint64_t m) {
+  unsigned long long first = 0;
+  if (lane_id() == 0) first = atomicAdd(cursor, (unsigned long long)__popcll(m));
+  first = __shfl(first, 0, 64);
+  return (int64_t)first + (int64_t)lanes_below(m);
+}
+
+// The leaf depth d = k-1 of a listing walk.  Its candidate set is formed as
+// dfs_level forms it (bounded base, membership probes, subtractions in
+// vertex-induced mode, explicit exclusion of matched vertices), one candidate
+// per lane, but is never reduced to a size: every surviving candidate
+// completes one match, written as a row in the caller's vertex ids.  A row at
+// or beyond out_cap is counted and not written.
+__device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
+                                          const int32_t* __restrict__ col, const ListArgs& a,
+                                          const LevelPlan& L, const DfsState& st, int d) {
+  int32_t bound = INT_MAX;
+  for (int j = 0; j < d; ++j)
+    if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
+  const int32_t* base;
+  int32_t blen;
+  int base_i = -1;
+  if (L.base_buf >= 0) {
+    base = st.set[L.base_buf];
+    blen = st.sz[L.base_buf];
+  } else {
+    blen = INT_MAX;
+    base = nullptr;
+    for (int i = 0; i < L.n_int; ++i) {
+      int32_t vj = st.v[L.int_lv[i]];
+      int32_t len = (int32_t)(rp[vj + 1] - rp[vj]);
+      if (len < blen) { blen = len; base_i = i; base = col + rp[vj]; }
+    }
+  }
+  blen = uni(lower_bound(base, uni(blen), bound));
+  // the caller's ids of the matched vertices, by depth
+  int32_t mv[kMaxK - 1];
+#pragma unroll
+  for (int j = 0; j < kMaxK - 1; ++j)
+    mv[j] = j < d ? (a.ids ? a.ids[st.v[j]] : st.v[j]) : 0;
+  const int l = lane_id();
+  for (int32_t ib = 0; ib < blen; ib += 64) {
+    const int32_t i = ib + l;
+    bool keep = i < blen;
+    const int32_t x = keep ? base[i] : 0;
+    for (int q = 0; q < L.n_int && keep; ++q) {
+      if (q == base_i) continue;
+      int32_t vj = st.v[L.int_lv[q]];
+      keep = member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int q = 0; q < L.n_sub && keep; ++q) {
+      int32_t vj = st.v[L.sub_lv[q]];
+      keep = !member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int j = 0; j < d && keep; ++j)
+      if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
+    const uint64_t m = wave_ballot(keep);
+    if (!m) continue;
+    const int64_t row = claim_rows(&a.cursor[1], m);
+    if (keep && row < a.out_cap) {
+      int32_t* o = a.out + row * a.k;
+#pragma unroll
+      for (int j = 0; j < kMaxK - 1; ++j)
+        if (j < d) o[a.out_col[j]] = mv[j];
+      o[a.out_col[d]] = a.ids ? a.ids[x] : x;
+    }
+  }
+}
+
+// All matches extending the root (v0, v1), for k >= 3: the walk of dfs_root
+// over depths 2 .. k-2 (stored or sliced candidate sets, wave-uniform), with
+// the leaf depth emitted by list_leaf.
+__device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const ListArgs& a, int32_t v0, int32_t v1, int32_t* fb,
+                          DfsState& st) {
+  const Plan& P = a.plan;
+  const int k = P.k;
+  ElemCounter ec;  // not reported for listing
+  st.v[0] = v0;
+  st.v[1] = v1;
+  if (k == 3) {
+    list_leaf(rp, col, a, P.lv[2], st, 2);
+    return;
+  }
+  int d = 2;
+  {
+    int32_t* out = fb + (size_t)(P.store_slot[2] < 0 ? 0 : P.store_slot[2]) * a.cap;
+    st.sz[2] = uni(dfs_level<true, false>(rp, col, P.lv[2], st, 2, out, ec));
+    st.ix[2] = 0;
+  }
+  for (;;) {
+    if (d == k - 2) {
+      for (int32_t i = 0; i < st.sz[d]; ++i) {
+        const int32_t x = uni(st.set[d][i]);
+        if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) continue;
+        st.v[d] = x;
+        list_leaf(rp, col, a, P.lv[d + 1], st, d + 1);
+      }
+      if (d == 2) break;
+      --d;
+      ++st.ix[d];
+      continue;
+    }
+    if (st.ix[d] >= st.sz[d]) {
+      if (d == 2) break;
+      --d;
+      ++st.ix[d];
+      continue;
+    }
+    const int32_t x = uni(st.set[d][st.ix[d]]);
+    if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) {
+      ++st.ix[d];
+      continue;
+    }
+    st.v[d] = x;
+    ++d;
+    int32_t* out = fb + (size_t)(P.store_slot[d] < 0 ? 0 : P.store_slot[d]) * a.cap;
+    st.sz[d] = uni(dfs_level<true, false>(rp, col, P.lv[d], st, d, out, ec));
+    st.ix[d] = 0;
+  }
+}
+
+// Persistent listing kernel: each wave pops chunks of root tasks from one
+// queue counter until the tasks run out.  For k <= 2 a root task is itself a
+// match (a vertex, or an edge taken once).
+__global__ void __launch_bounds__(kWavesPerBlock * 64) gpm_list(ListArgs a) {
+  const int w = threadIdx.x >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  int32_t* fb = a.fbuf ? a.fbuf + gw * a.wave_stride : nullptr;
+  DfsState st;
+  for (;;) {
+    unsigned long long c = 0;
+    if (lane_id() == 0) c = atomicAdd(&a.cursor[0], 1ull);
+    c = __shfl(c, 0, 64);
+    const int64_t t0 = (int64_t)c * a.chunk;
+    if (t0 >= a.n_tasks) break;
+    const int64_t t1 = min(t0 + (int64_t)a.chunk, a.n_tasks);
+    if (a.k <= 2) {
+      for (int64_t tb = t0; tb < t1; tb += 64) {
+        const int64_t t = tb + lane_id();
+        const bool keep = t < t1;
+        const int64_t row = claim_rows(&a.cursor[1], wave_ballot(keep));
+        if (keep && row < a.out_cap) {
+          int32_t* o = a.out + row * a.k;
+          const int32_t u = a.task_src ? a.task_src[t] : (int32_t)t;
+          o[a.out_col[0]] = a.ids ? a.ids[u] : u;
+          if (a.k == 2) {
+            const int32_t v = a.task_dst[t];
+            o[a.out_col[1]] = a.ids ? a.ids[v] : v;
+          }
+        }
+      }
+      continue;
+    }
+    for (int64_t t = t0; t < t1; ++t)
+      list_root(a.rp, a.col, a, uni(a.task_src[t]), uni(a.task_dst[t]), fb, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
 
@@ -1619,6 +1784,12 @@ int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max
     hipLaunchKernelGGL(gpm_lgs_block<true>, dim3((unsigned)blocks), dim3(kBlockWaves * 64), lds_bytes, s, a);
   else
     hipLaunchKernelGGL(gpm_lgs_block<false>, dim3((unsigned)blocks), dim3(kBlockWaves * 64), lds_bytes, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_list(const ListArgs& a, int blocks, void* stream) {
+  hipLaunchKernelGGL(gpm_list, dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), 0,
+                     (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ struct Graph {
   // a symmetry bound v_j < v_i also bounds degree (lazy)
   HostCSR ren_host;
   GraphView ren;
+  int32_t* ren_ids = nullptr;   // relabelled id -> caller's id (listing output)
   int32_t* ren_lo_src = nullptr;
   int32_t* ren_lo_dst = nullptr;
   int64_t ren_n_lo = 0;
@@ -173,6 +174,9 @@ struct gpm_ctx {
   int64_t opt_serve_light_ms = 50;
   int64_t next_ticket = 1;
   size_t serve_frontier_in_use = 0;
+  // listing: queue and match counters (device), their copy (pinned host)
+  unsigned long long* d_list = nullptr;
+  unsigned long long* h_list = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -214,6 +218,8 @@ static void free_view(GraphView& v) {
 static void free_graph(Graph& g) {
   free_view(g.sym);
   free_view(g.ren);
+  dev_free(g.ren_ids);
+  g.ren_ids = nullptr;
   dev_free(g.wedge_src);
   dev_free(g.wedge_dst);
   g.wedge_src = g.wedge_dst = nullptr;
@@ -473,6 +479,9 @@ static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
   if (st) return st;
   st = lower_edges(c, R, &g.ren_lo_src, &g.ren_lo_dst, &g.ren_n_lo, &g.bytes);
   if (st) return st;
+  st = dev_upload(c, &g.ren_ids, order.data(), order.size());
+  if (st) return st;
+  g.bytes += order.size() * 4;
   g.ren_ready = true;
   return GPM_OK;
 }
@@ -1803,6 +1812,8 @@ gpm_status gpm_destroy(gpm_ctx* c) {
   (void)hipSetDevice(c->device);
   for (auto& s : c->slots) slot_free(s);
   for (auto& kv : c->graphs) free_graph(*kv.second);
+  dev_free(c->d_list);
+  if (c->h_list) (void)hipHostFree(c->h_list);
   delete c;
   return GPM_OK;
 }
@@ -2093,6 +2104,144 @@ gpm_status gpm_motifs(gpm_ctx* c, int32_t graph_id, int k, uint64_t* counts_out,
   st = run_sync(c, js, qs, true, out);
   if (st) return st;
   for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts_out[i] = out[i];
+  return GPM_OK;
+}
+
+gpm_status gpm_list(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, int mode,
+                    int32_t* out, int64_t cap, uint64_t* count_out) {
+  if (!c || !pattern || !count_out) return GPM_E_INVAL;
+  if (cap < 0 || (cap > 0 && !out)) return fail(c, GPM_E_INVAL, "bad output buffer");
+  if (mode != GPM_VERTEX_INDUCED && mode != GPM_EDGE_INDUCED)
+    return fail(c, GPM_E_INVAL, "bad induced mode");
+  HIP_TRY(c, hipSetDevice(c->device));
+  Graph* gp = find_graph(c, graph_id);
+  if (!gp) return fail(c, GPM_E_INVAL, "unknown graph id");
+  Graph& g = *gp;
+  const gpm_pattern& p = *pattern;
+  std::string err;
+  gpm_status st = validate_pattern(p, &err);
+  if (st) return fail(c, st, err);
+  const bool clique = is_clique(p);
+  if (g.dag_only && !clique)
+    return fail(c, GPM_E_UNSUPPORTED, "non-clique pattern on a DAG-only graph");
+  c->stats = gpm_stats{};
+  c->stats.elements = c->stats.list_fetches = c->stats.frontier_written = -1;
+  c->stats.bitmap_words = -1;
+  const int64_t n = g.host.n;
+  if (n < p.k || (p.k >= 2 && g.m == 0)) {
+    *count_out = 0;
+    return GPM_OK;
+  }
+
+  ListArgs a{};
+  a.k = p.k;
+  a.out = out;
+  a.out_cap = cap;
+  HostPlan hp;
+  // cliques (k >= 2) on the DAG: each clique once, with no symmetry bounds;
+  // other patterns on the symmetric graph (relabelled unless "rename" is 0)
+  const bool on_dag = clique && p.k >= 2;
+  st = build_plan(p, mode, on_dag, &hp, &err);
+  if (st) return fail(c, st, err);
+  a.plan = hp.plan;
+  for (int d = 0; d < p.k; ++d) a.out_col[d] = (int8_t)hp.order[d];
+  GraphView* V = nullptr;
+  if (on_dag) {
+    st = ensure_dag(c, g);
+    if (st) return st;
+    V = &g.dag;
+    a.ids = g.dag_only ? nullptr : g.ren_ids;
+    a.task_src = g.dag.src;
+    a.task_dst = g.dag.col;
+    a.n_tasks = g.dag.nnz;
+  } else {
+    const bool ren = c->opt_rename != 0 && !g.dag_only;
+    if (ren) {
+      st = ensure_ren(c, g);
+      if (st) return st;
+    }
+    V = g.dag_only ? &g.dag : (ren ? &g.ren : &g.sym);
+    if (g.dag_only) {
+      st = ensure_dag(c, g);
+      if (st) return st;
+    }
+    a.ids = ren ? g.ren_ids : nullptr;
+    if (p.k == 1) {
+      a.n_tasks = n;  // vertex tasks
+    } else if (ren) {
+      // root edges (v0, v1) with v1 < v0: every plan of k >= 2 bounds v1 by
+      // v0 or is a clique (on the DAG above)
+      a.task_src = g.ren_lo_src;
+      a.task_dst = g.ren_lo_dst;
+      a.n_tasks = g.ren_n_lo;
+    } else {
+      st = ensure_lower(c, g);
+      if (st) return st;
+      a.task_src = g.lo_src;
+      a.task_dst = g.lo_dst;
+      a.n_tasks = g.n_lo;
+    }
+    if (p.k >= 2 && !hp.plan.root_bound) {
+      // a root edge with no bound would need both directions
+      if (!V->src) {
+        const HostCSR& H = ren ? g.ren_host : g.host;
+        std::vector<int32_t> src(H.col.size());
+        for (int64_t u = 0; u < n; ++u)
+          for (int64_t q = H.rp[u]; q < H.rp[u + 1]; ++q) src[q] = (int32_t)u;
+        st = dev_upload(c, &V->src, src.data(), src.size());
+        if (st) return st;
+        g.bytes += src.size() * 4;
+      }
+      a.task_src = V->src;
+      a.task_dst = V->col;
+      a.n_tasks = V->nnz;
+    }
+  }
+  a.rp = V->rp;
+  a.col = V->col;
+  const int64_t fcap = std::max<int64_t>(V->max_deg, 1);
+  a.cap = (int32_t)fcap;
+  a.chunk = p.k <= 2 ? 4096 : 8;
+
+  Slot& s = c->slots[0];
+  s.stream = c->user_stream;
+  st = slot_init(c, s, s.stream);
+  if (st) return st;
+  const int64_t stride = (int64_t)align_up((size_t)(hp.n_buffers * fcap), 64);
+  const int64_t max_resident = (int64_t)c->cus * 16;
+  int64_t waves = max_resident;
+  if (stride > 0) {
+    const size_t budget = c->budget > c->serve_frontier_in_use ? c->budget - c->serve_frontier_in_use : 0;
+    gpm_status s2 = gpm_frontier_waves((int64_t)budget, 1, stride, max_resident, max_resident, &waves);
+    if (s2 || waves < kWavesPerBlock)
+      return fail(c, GPM_E_NOMEM, "frontier buffers do not fit the memory budget");
+  }
+  waves = std::max<int64_t>(kWavesPerBlock, waves / kWavesPerBlock * kWavesPerBlock);
+  const int blocks = (int)(waves / kWavesPerBlock);
+  if (stride > 0) {
+    st = grow_dev(c, (void**)&s.d_fbuf, &s.d_fbuf_bytes, (size_t)waves * (size_t)stride * 4);
+    if (st) return st;
+    a.fbuf = s.d_fbuf;
+    a.wave_stride = stride;
+  }
+  if (!c->d_list) HIP_TRY(c, hipMalloc((void**)&c->d_list, 2 * sizeof(unsigned long long)));
+  if (!c->h_list)
+    HIP_TRY(c, hipHostMalloc((void**)&c->h_list, 2 * sizeof(unsigned long long), hipHostMallocDefault));
+  a.cursor = c->d_list;
+  auto t0 = std::chrono::steady_clock::now();
+  if (launch_fill_u64(c->d_list, 2, 0ull, s.stream))
+    return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+  HIP_TRY(c, hipEventRecord(s.ev0, s.stream));
+  if (launch_list(a, blocks, s.stream)) return fail(c, GPM_E_DEVICE, "listing kernel launch failed");
+  HIP_TRY(c, hipEventRecord(s.ev1, s.stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_list, c->d_list, 2 * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s.stream));
+  HIP_TRY(c, hipStreamSynchronize(s.stream));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
+  c->stats.kernel_ms = ms;
+  c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *count_out = (uint64_t)c->h_list[1];
   return GPM_OK;
 }
 

@@ -40,7 +40,7 @@ EXPORTS = [
     "gpm_load_csr", "gpm_unload", "gpm_graph_info", "gpm_pattern_clique",
     "gpm_pattern_named", "gpm_pattern_from_edges", "gpm_plan", "gpm_frontier_waves",
     "gpm_count", "gpm_motifs", "gpm_count_batch", "gpm_submit", "gpm_poll", "gpm_wait",
-    "gpm_inflight", "gpm_validate_csr", "gpm_prepare",
+    "gpm_inflight", "gpm_validate_csr", "gpm_prepare", "gpm_list",
 ]
 
 
@@ -135,6 +135,7 @@ def lib():
         L.gpm_frontier_waves.argtypes = [c_i64, c_i32, c_i64, c_i64, c_i64, P(c_i64)]
         L.gpm_count.argtypes = [c_vp, c_i32, P(Pattern), ctypes.c_int, P(c_u64)]
         L.gpm_motifs.argtypes = [c_vp, c_i32, ctypes.c_int, P(c_u64), c_sz]
+        L.gpm_list.argtypes = [c_vp, c_i32, P(Pattern), ctypes.c_int, c_vp, c_i64, P(c_u64)]
         L.gpm_count_batch.argtypes = [c_vp, c_i32, P(Query), P(c_u64)]
         L.gpm_submit.argtypes = [c_vp, P(Query), P(c_i64)]
         L.gpm_poll.argtypes = [c_vp, c_i64, P(ctypes.c_int), P(c_u64)]
@@ -329,6 +330,22 @@ class Context:
         p = as_pattern(pattern)
         self._ck(lib().gpm_count(self._h, graph_id, ctypes.byref(p), mode, ctypes.byref(out)))
         return out.value
+
+    def list(self, graph_id: int, pattern, out, mode: int = GPM_VERTEX_INDUCED) -> int:
+        """gpm_list into `out`, an int32 device tensor of shape [cap, k] on the
+        context's device; returns the total number of matches (rows beyond
+        out.shape[0] were counted, not written)."""
+        import torch
+        p = as_pattern(pattern)
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 device tensor")
+        if out.dim() != 2 or out.shape[1] != p.k:
+            raise ValueError(f"out must have shape [cap, {p.k}]")
+        total = c_u64()
+        ptr = c_vp(out.data_ptr()) if out.shape[0] > 0 else None
+        self._ck(lib().gpm_list(self._h, graph_id, ctypes.byref(p), mode, ptr,
+                                int(out.shape[0]), ctypes.byref(total)))
+        return total.value
 
     def motifs(self, graph_id: int, k: int):
         n = 2 if k == 3 else 6

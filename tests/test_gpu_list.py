@@ -1,0 +1,266 @@
+"""Parity of gpm_list (subgraph listing, Sec. 2.1) with the CPU oracle.
+
+Rows come back in an unspecified order and as any one embedding of each
+subgraph, so each GPU row is reduced to the smallest of its automorphic
+images -- the representative the oracle emits -- and the sorted rows are
+compared element by element.  At sizes beyond the oracle's listing, the
+rows are checked by properties that hold at any size: every row is a valid
+match, no two rows are the same subgraph, and their number equals the
+oracle's count (together these make the rows exactly the set of matches).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2112_09761_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+V, E = 0, 1
+NAMES = ["triangle", "wedge", "path4", "star3", "cycle4", "tailed_triangle",
+         "diamond", "clique4", "clique5"]
+HOUSE = (5, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (1, 4)])
+SIX = (6, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (5, 3)])  # two linked triangles
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2112_09761_amd import gpm
+    assert torch.cuda.is_available()
+    c = gpm.Context(0, torch.cuda.current_stream())
+    yield c
+    c.close()
+
+
+def pattern_of(oracle, p):
+    return oracle.PATTERNS[p] if isinstance(p, str) else p
+
+
+def automorphisms(k, edges):
+    es = {frozenset(e) for e in edges}
+    return [list(p) for p in itertools.permutations(range(k))
+            if {frozenset((p[a], p[b])) for a, b in edges} == es]
+
+
+def canonical(rows, k, edges):
+    """Each row replaced by the lexicographically smallest of its automorphic
+    images, rows sorted."""
+    rows = np.asarray(rows, dtype=np.int64).reshape(-1, k)
+    best = rows.copy()
+    for s in automorphisms(k, edges):
+        img = rows[:, s]
+        less = np.zeros(len(rows), dtype=bool)
+        eq = np.ones(len(rows), dtype=bool)
+        for j in range(k):
+            less |= eq & (img[:, j] < best[:, j])
+            eq &= img[:, j] == best[:, j]
+        best[less] = img[less]
+    order = np.lexsort(best.T[::-1]) if len(best) else np.zeros(0, dtype=np.int64)
+    return best[order]
+
+
+def run_list(ctx, gid, pattern, mode, cap, k, guard=16):
+    """gpm_list into the first cap rows of a larger buffer whose guard rows
+    must stay untouched."""
+    import torch
+    buf = torch.full((cap + guard, k), -7, dtype=torch.int32, device="cuda")
+    total = ctx.list(gid, pattern, buf[:cap], mode)
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert (h[cap:] == -7).all(), "rows written past cap"
+    return h[:min(cap, total)], total
+
+
+def check_against_oracle(ctx, oracle, g, gid, p, mode, cap=None):
+    k, edges = pattern_of(oracle, p)
+    exp, cnt = oracle.list_embed(g, pattern_of(oracle, p), mode == V, cap=cap)
+    rows, total = run_list(ctx, gid, p, mode, cnt + 5, k)
+    assert total == cnt, (g.name, p, mode, total, cnt)
+    assert total == ctx.count(gid, p, mode)
+    assert np.array_equal(canonical(rows, k, edges), canonical(exp, k, edges)), (g.name, p, mode)
+
+
+def graphs():
+    return [
+        synth.complete(8),
+        synth.complete_bipartite(4, 6),
+        synth.grid(5, 7),
+        synth.star(30),
+        synth.cycle(11),
+        synth.erdos_renyi(70, 0.15, 301),
+        synth.rmat(8, 6, seed=302),
+        synth.chung_lu(300, 6.0, 2.1, 60.0, 900, 303),
+        synth.disjoint_union(synth.complete(6), synth.empty(5), synth.cycle(4)),
+    ]
+
+
+@pytest.mark.parametrize("gi", range(9))
+def test_list_named_patterns(ctx, oracle, gi):
+    g = graphs()[gi]
+    gid = ctx.load(g)
+    try:
+        for p in NAMES + [HOUSE]:
+            for mode in (V, E):
+                check_against_oracle(ctx, oracle, g, gid, p, mode)
+    finally:
+        ctx.unload(gid)
+
+
+def test_list_er_triangle_workload(ctx, oracle):
+    # Erdos-Renyi G(2000, 0.01): about 1.3k triangles over ~20k edges
+    g = synth.erdos_renyi(2000, 0.01, 1)
+    gid = ctx.load(g)
+    try:
+        check_against_oracle(ctx, oracle, g, gid, "triangle", V)
+        check_against_oracle(ctx, oracle, g, gid, "wedge", V)
+        check_against_oracle(ctx, oracle, g, gid, "cycle4", E)
+    finally:
+        ctx.unload(gid)
+
+
+def test_list_six_vertex_pattern_and_cliques_to_eight(ctx, oracle):
+    g = synth.erdos_renyi(25, 0.3, 311)
+    gid = ctx.load(g)
+    try:
+        for mode in (V, E):
+            check_against_oracle(ctx, oracle, g, gid, SIX, mode)
+    finally:
+        ctx.unload(gid)
+    g = synth.erdos_renyi(34, 0.6, 312)
+    gid = ctx.load(g)
+    try:
+        for k in (6, 7, 8):
+            check_against_oracle(ctx, oracle, g, gid, oracle.clique(k), V,
+                                 cap=oracle.cliques(g, k))
+    finally:
+        ctx.unload(gid)
+
+
+def test_list_without_relabelling(ctx, oracle):
+    g = synth.rmat(8, 8, seed=321)
+    gid = ctx.load(g)
+    ctx.set_option("rename", 0)
+    try:
+        for p in ["path4", "tailed_triangle", "cycle4", HOUSE]:
+            for mode in (V, E):
+                check_against_oracle(ctx, oracle, g, gid, p, mode)
+    finally:
+        ctx.set_option("rename", 1)
+        ctx.unload(gid)
+
+
+def test_list_overflow(ctx, oracle):
+    g = synth.erdos_renyi(200, 0.1, 331)
+    gid = ctx.load(g)
+    try:
+        for p, mode in (("triangle", V), ("diamond", E), ("clique4", V), ("wedge", V)):
+            k, edges = pattern_of(oracle, p)
+            exp, cnt = oracle.list_embed(g, pattern_of(oracle, p), mode == V)
+            full = {tuple(r) for r in canonical(exp, k, edges)}
+            for cap in (0, 1, 63, 64, 65, cnt // 2, cnt - 1):
+                rows, total = run_list(ctx, gid, p, mode, cap, k)
+                assert total == cnt and len(rows) == min(cap, cnt)
+                got = [tuple(r) for r in canonical(rows, k, edges)]
+                assert len(set(got)) == len(got), "a match written twice"
+                assert set(got) <= full, "a row that is not a match"
+    finally:
+        ctx.unload(gid)
+
+
+def test_list_small_cases(ctx, oracle):
+    g = synth.erdos_renyi(50, 0.1, 341)
+    gid = ctx.load(g)
+    try:
+        rows, total = run_list(ctx, gid, (1, []), V, g.n, 1)
+        assert total == g.n and sorted(rows[:, 0].tolist()) == list(range(g.n))
+        rows, total = run_list(ctx, gid, "edge", V, g.m, 2)
+        assert total == g.m
+        exp = {frozenset(e) for e in zip(*[x.tolist() for x in synth.to_edge_list(g)])}
+        assert {frozenset(r.tolist()) for r in rows} == exp and len(rows) == len(exp)
+    finally:
+        ctx.unload(gid)
+    for g in (synth.empty(6), synth.complete(3)):
+        gid = ctx.load(g)
+        try:
+            _, total = run_list(ctx, gid, "clique4", V, 4, 4)
+            assert total == 0
+            _, total = run_list(ctx, gid, "edge", V, 4, 2)
+            assert total == g.m
+        finally:
+            ctx.unload(gid)
+
+
+def test_list_dag_input(ctx, oracle):
+    from paper_2112_09761_amd import gpm
+    g = synth.erdos_renyi(300, 0.1, 351)
+    # the DAG u -> v iff u < v, in the caller's ids
+    rp, col = g.row_ptr, g.col
+    src = np.repeat(np.arange(g.n), np.diff(rp))
+    keep = col > src
+    drp = np.zeros(g.n + 1, dtype=np.int64)
+    np.add.at(drp, src[keep] + 1, 1)
+    drp = np.cumsum(drp)
+    gid = ctx.load_csr(drp, col[keep].astype(np.int32), gpm.GPM_CSR_DAG)
+    try:
+        for k in (3, 4, 5):
+            pat = oracle.clique(k)
+            exp, cnt = oracle.list_embed(g, pat, True)
+            rows, total = run_list(ctx, gid, pat, V, cnt + 3, k)
+            assert total == cnt
+            assert np.array_equal(canonical(rows, k, pat[1]), canonical(exp, k, pat[1]))
+        with pytest.raises(gpm.GpmError):
+            run_list(ctx, gid, "cycle4", E, 4, 4)
+    finally:
+        ctx.unload(gid)
+
+
+def has_edges(g, u, v):
+    """Vectorised adjacency test on the sorted CSR."""
+    lo = g.row_ptr[u]
+    deg = g.row_ptr[u + 1] - lo
+    out = np.zeros(len(u), dtype=bool)
+    for i in range(len(u)):
+        if deg[i]:
+            j = np.searchsorted(g.col[lo[i]:lo[i] + deg[i]], v[i])
+            out[i] = j < deg[i] and g.col[lo[i] + j] == v[i]
+    return out
+
+
+def test_list_rmat_cliques_by_properties(ctx, oracle):
+    import torch
+    g = synth.rmat(12, 8, seed=361)
+    gid = ctx.load(g)
+    try:
+        for k in (4, 5):
+            cnt = oracle.cliques(g, k)
+            buf = torch.empty((cnt, k), dtype=torch.int32, device="cuda")
+            total = ctx.list(gid, oracle.clique(k), buf, V)
+            assert total == cnt
+            rows = np.sort(buf.cpu().numpy().astype(np.int64), axis=1)
+            # distinct vertex sets
+            assert len(np.unique(rows, axis=0)) == cnt
+            # every pair adjacent (and so every row a k-clique); a sample of rows
+            rng = np.random.default_rng(5)
+            pick = rng.choice(cnt, size=min(cnt, 4000), replace=False)
+            for a, b in itertools.combinations(range(k), 2):
+                assert has_edges(g, rows[pick, a], rows[pick, b]).all()
+    finally:
+        ctx.unload(gid)
+
+
+def test_list_errors(ctx):
+    import torch
+    from paper_2112_09761_amd import gpm
+    g = synth.complete(5)
+    gid = ctx.load(g)
+    try:
+        with pytest.raises(ValueError):
+            ctx.list(gid, "triangle", torch.empty((4, 4), dtype=torch.int32, device="cuda"))
+        with pytest.raises(gpm.GpmError):
+            ctx.list(gid, (3, [(0, 1)]), torch.empty((4, 3), dtype=torch.int32, device="cuda"))
+        with pytest.raises(gpm.GpmError):
+            ctx.list(gid + 999, "triangle", torch.empty((4, 3), dtype=torch.int32, device="cuda"))
+    finally:
+        ctx.unload(gid)
