@@ -9,7 +9,7 @@ before the timed region, as in the paper's evaluation.
 Prints ONE JSON line: intersected elements/s over the timed steps, the
 roofline of the dominant kernel (the longest launch of a step) and the CPU oracle's
 rate on a bounded sample.  Other workloads (--workload batch | serve |
-triangle) print their own line.
+triangle | chunglu | list) print their own line.
 """
 import argparse
 import json
@@ -31,8 +31,8 @@ WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
 # for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
 # the kernel sources they were taken on (and that launch) only; else null.
-TRAFFIC = {"sources_sha256": "bc5cfd18359fc68ea14b069a8352d352aa22a55551fdc82399a5ba94a59ecd6e",
-           "k": 5, "kinds": 1 << 7, "fetch_kib": 1845234.3, "write_kib": 866.2,
+TRAFFIC = {"sources_sha256": "3dd68a0b0870d04c53066acc8c87d68cc3be7d759d5326962a572d5898a0b81e",
+           "k": 5, "kinds": 1 << 7, "fetch_kib": 1844383.0, "write_kib": 866.2,
            "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
 
@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="clique",
-                    choices=["clique", "triangle", "chunglu", "batch", "serve"])
+                    choices=["clique", "triangle", "chunglu", "batch", "serve", "list"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default kernel knobs (fixed dispatch sequence)")
@@ -85,6 +85,20 @@ def measured_traffic(k, kinds):
         return None
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] +
                      TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+
+
+# gpm_list on the listing workload: the same two counter passes (KiB per
+# dispatch), valid for the sources they were taken on
+LIST_TRAFFIC = {"sources_sha256": "3dd68a0b0870d04c53066acc8c87d68cc3be7d759d5326962a572d5898a0b81e",
+                "fetch_kib": 154205.3, "write_kib": 5026110.5,
+                "fetch_factor": 2.0, "write_factor": 1.0}
+
+
+def measured_list_traffic():
+    if not LIST_TRAFFIC["sources_sha256"] or LIST_TRAFFIC["sources_sha256"] != sources_sha256():
+        return None
+    return 1024.0 * (LIST_TRAFFIC["fetch_kib"] * LIST_TRAFFIC["fetch_factor"] +
+                     LIST_TRAFFIC["write_kib"] * LIST_TRAFFIC["write_factor"])
 
 
 def cpu_baseline_clique4(g, elements4):
@@ -234,6 +248,93 @@ def run_triangle(args, ctx, torch):
             "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
             "config": {"workload": "er_2000_p0.01_triangle"}, "count": c,
             "kernel_ms": statistics.mean(ms), "elements": inst["elements"]}
+
+
+def rows_are_cliques(g, rows):
+    """Every row k distinct vertices, every pair adjacent (sorted CSR lookup)."""
+    import numpy as np
+    rows = rows.astype(np.int64)
+    k = rows.shape[1]
+    if (np.sort(rows, axis=1)[:, 1:] == np.sort(rows, axis=1)[:, :-1]).any():
+        return False
+    for a in range(k):
+        for b in range(a + 1, k):
+            u, v = rows[:, a], rows[:, b]
+            lo, hi = g.row_ptr[u], g.row_ptr[u + 1]
+            for i in range(len(u)):
+                j = lo[i] + np.searchsorted(g.col[lo[i]:hi[i]], v[i])
+                if j >= hi[i] or g.col[j] != v[i]:
+                    return False
+    return True
+
+
+def cpu_baseline_list():
+    from oracle import pyoracle
+    from paper_2112_09761_amd import synth
+    progress("CPU oracle baseline (4-clique listing, R-MAT scale 11)")
+    g = synth.rmat(11, 16, 0.57, 0.19, 0.19, 1)
+    cap = pyoracle.cliques(g, 4, 1)
+    t = time.perf_counter()
+    _, c = pyoracle.list_embed(g, pyoracle.clique(4), True, cap=cap)
+    dt = time.perf_counter() - t
+    return {"value": c / dt, "unit": "matches/s", "cores": 1, "kind": "oracle",
+            "sample": f"4-clique listing of R-MAT scale 11, edge factor 16 (same generator, "
+                      f"1/32 of the vertices): {c} rows in {dt:.1f} s (serial routine)"}
+
+
+def run_list(args, ctx, torch):
+    """4-clique listing (gpm_list) on R-MAT scale 16, edge factor 16: every
+    4-clique written once as a row of 4 vertex ids into a device buffer sized
+    for all of them (4.7 GB); one step = one gpm_list call."""
+    import numpy as np
+    from paper_2112_09761_amd import synth
+    g = synth.workload_rmat_s16()
+    gid = ctx.load(g)
+    ctx.graph_info(gid)
+    pat = (4, [(i, j) for i in range(4) for j in range(i + 1, 4)])
+    total = ctx.count(gid, pat)   # sizes the buffer (untimed)
+    buf = torch.empty((total, 4), dtype=torch.int32, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        ctx.list(gid, pat, buf)
+    torch.cuda.synchronize()
+    progress("warm-up done")
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        n = ctx.list(gid, pat, buf)
+        kms.append(ctx.stats()["kernel_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gold = golden("rmat_s16")
+    parity = None
+    if gold and gold["sha256"] == g.sha256():
+        rng = np.random.default_rng(11)
+        pick = torch.from_numpy(rng.choice(n, size=min(n, 20000), replace=False)).cuda()
+        sample = buf[pick].cpu().numpy()
+        parity = bool(n == gold["counts"]["clique4"] and rows_are_cliques(g, sample))
+    launch_ms = statistics.mean(kms)
+    cms = []
+    for _ in range(3):  # the same 4-cliques counted (context for the listing cost)
+        ctx.count(gid, pat)
+        cms.append(ctx.stats()["kernel_ms"])
+    # algorithmic bytes of the launch: the rows written plus one read of the
+    # degree-oriented DAG (offsets and out-lists)
+    dag_bytes = 8 * (g.n + 1) + 4 * g.m
+    byts = 16 * n + dag_bytes
+    gbs = byts / (launch_ms * 1e-3) / 1e9
+    return {"metric": "4-cliques listed/s (rows written to HBM)", "value": n * args.steps / dt,
+            "unit": "matches/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "rmat_s16_ef16_list_clique4", "n": g.n, "m": g.m,
+                       "rows": n, "row_bytes": 16},
+            "parity_vs_stored_oracle": parity, "kernel_ms": launch_ms,
+            "count_kernel_ms": statistics.mean(cms),
+            "roofline": {"bound": "hbm", "kernel": "gpm_list (plan-driven walk, rows staged in LDS)",
+                         "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": measured_list_traffic(),
+                         "algorithmic_bytes_per_launch": byts, "launch_ms": launch_ms}}
 
 
 def run_chunglu(args, ctx, torch):
@@ -488,6 +589,9 @@ def main():
         out = run_triangle(args, ctx, torch)
     elif args.workload == "batch":
         out = run_batch(args, ctx, torch)
+    elif args.workload == "list":
+        out = run_list(args, ctx, torch)
+        out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_list()
     else:
         out = run_serve(args, ctx, torch)
     ctx.close()

@@ -166,7 +166,8 @@ struct ListArgs {
   const int32_t* ids;        // view id -> caller's vertex id; null: identity
   int32_t* out;              // rows [out_cap][k]
   int64_t out_cap;
-  unsigned long long* cursor;  // [0]: next chunk, [1]: matches found (rows claimed)
+  unsigned long long* queue;   // next chunk of the root tasks
+  unsigned long long* rows;    // matches found (rows claimed)
   int32_t* fbuf;             // frontier buffers: wave_stride words per wave
   int64_t wave_stride;
 };

@@ -1218,24 +1218,47 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
 // listing (Sec. 2.1: every match is enumerated instead of counted)
 // ---------------------------------------------------------------------------
 
-// Claim rows for the lanes set in m (one atomic per wave) and return this
-// lane's row: the lanes' rows are consecutive in lane order.
-__device__ __forceinline__ int64_t claim_rows(unsigned long long* cursor, uint64_t m) {
+// Rows are staged per wave in LDS and written out in groups: one atomic
+// claim of the group's rows on the shared row counter, then a contiguous,
+// coalesced copy.  (A claim per 64-candidate batch serialises the whole
+// grid on that one counter.)
+constexpr int kListStageWords = 2048;   // int32 words of staged rows per wave
+
+// Write the wave's n staged rows (row-major, k words each) to the output and
+// empty the stage; rows at or beyond out_cap are counted and dropped.
+__device__ __forceinline__ void list_flush(const ListArgs& a, const int32_t* stage, int32_t& n) {
+  if (n == 0) return;
+  wave_sync_mem();
   unsigned long long first = 0;
-  if (lane_id() == 0) first = atomicAdd(cursor, (unsigned long long)__popcll(m));
-  first = __shfl(first, 0, 64);
-  return (int64_t)first + (int64_t)lanes_below(m);
+  if (lane_id() == 0) first = atomicAdd(a.rows, (unsigned long long)n);
+  const int64_t row0 = (int64_t)__shfl(first, 0, 64);
+  const int64_t fit = min((int64_t)n, a.out_cap - row0);
+  if (fit > 0) {
+    int32_t* o = a.out + row0 * a.k;
+    const int32_t words = (int32_t)fit * a.k;
+    for (int32_t i = lane_id(); i < words; i += 64) o[i] = stage[i];
+  }
+  n = 0;
+  wave_sync_mem();
+}
+
+// Stage the rows of the lanes set in m (this lane's row when keep); flush
+// once another full batch might not fit.  The stage holds stage_rows rows,
+// and n <= stage_rows - 64 holds before every batch.
+__device__ __forceinline__ int32_t* stage_row(int32_t* stage, int32_t n, uint64_t m, int k) {
+  return stage + (n + (int32_t)lanes_below(m)) * k;
 }
 
 // The leaf depth d = k-1 of a listing walk.  Its candidate set is formed as
 // dfs_level forms it (bounded base, membership probes, subtractions in
 // vertex-induced mode, explicit exclusion of matched vertices), one candidate
 // per lane, but is never reduced to a size: every surviving candidate
-// completes one match, written as a row in the caller's vertex ids.  A row at
-// or beyond out_cap is counted and not written.
+// completes one match, staged as a row in the caller's vertex ids.
 __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
                                           const int32_t* __restrict__ col, const ListArgs& a,
-                                          const LevelPlan& L, const DfsState& st, int d) {
+                                          const LevelPlan& L, const DfsState& st, int d,
+                                          int32_t* stage, int32_t& stage_n,
+                                          int32_t stage_rows) {
   int32_t bound = INT_MAX;
   for (int j = 0; j < d; ++j)
     if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
@@ -1278,14 +1301,15 @@ __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
       if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
     const uint64_t m = wave_ballot(keep);
     if (!m) continue;
-    const int64_t row = claim_rows(&a.cursor[1], m);
-    if (keep && row < a.out_cap) {
-      int32_t* o = a.out + row * a.k;
+    if (keep) {
+      int32_t* o = stage_row(stage, stage_n, m, a.k);
 #pragma unroll
       for (int j = 0; j < kMaxK - 1; ++j)
         if (j < d) o[a.out_col[j]] = mv[j];
       o[a.out_col[d]] = a.ids ? a.ids[x] : x;
     }
+    stage_n += (int32_t)__popcll(m);
+    if (stage_n > stage_rows - 64) list_flush(a, stage, stage_n);
   }
 }
 
@@ -1294,14 +1318,14 @@ __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
 // the leaf depth emitted by list_leaf.
 __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                           const ListArgs& a, int32_t v0, int32_t v1, int32_t* fb,
-                          DfsState& st) {
+                          DfsState& st, int32_t* stage, int32_t& stage_n, int32_t stage_rows) {
   const Plan& P = a.plan;
   const int k = P.k;
   ElemCounter ec;  // not reported for listing
   st.v[0] = v0;
   st.v[1] = v1;
   if (k == 3) {
-    list_leaf(rp, col, a, P.lv[2], st, 2);
+    list_leaf(rp, col, a, P.lv[2], st, 2, stage, stage_n, stage_rows);
     return;
   }
   int d = 2;
@@ -1316,7 +1340,7 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
         const int32_t x = uni(st.set[d][i]);
         if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) continue;
         st.v[d] = x;
-        list_leaf(rp, col, a, P.lv[d + 1], st, d + 1);
+        list_leaf(rp, col, a, P.lv[d + 1], st, d + 1, stage, stage_n, stage_rows);
       }
       if (d == 2) break;
       --d;
@@ -1346,13 +1370,17 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
 // queue counter until the tasks run out.  For k <= 2 a root task is itself a
 // match (a vertex, or an edge taken once).
 __global__ void __launch_bounds__(kWavesPerBlock * 64) gpm_list(ListArgs a) {
+  __shared__ int32_t list_stage[kWavesPerBlock][kListStageWords];
   const int w = threadIdx.x >> 6;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + w;
   int32_t* fb = a.fbuf ? a.fbuf + gw * a.wave_stride : nullptr;
+  int32_t* stage = list_stage[w];
+  const int32_t stage_rows = kListStageWords / a.k;
+  int32_t stage_n = 0;
   DfsState st;
   for (;;) {
     unsigned long long c = 0;
-    if (lane_id() == 0) c = atomicAdd(&a.cursor[0], 1ull);
+    if (lane_id() == 0) c = atomicAdd(a.queue, 1ull);
     c = __shfl(c, 0, 64);
     const int64_t t0 = (int64_t)c * a.chunk;
     if (t0 >= a.n_tasks) break;
@@ -1361,9 +1389,9 @@ __global__ void __launch_bounds__(kWavesPerBlock * 64) gpm_list(ListArgs a) {
       for (int64_t tb = t0; tb < t1; tb += 64) {
         const int64_t t = tb + lane_id();
         const bool keep = t < t1;
-        const int64_t row = claim_rows(&a.cursor[1], wave_ballot(keep));
-        if (keep && row < a.out_cap) {
-          int32_t* o = a.out + row * a.k;
+        const uint64_t m = wave_ballot(keep);
+        if (keep) {
+          int32_t* o = stage_row(stage, stage_n, m, a.k);
           const int32_t u = a.task_src ? a.task_src[t] : (int32_t)t;
           o[a.out_col[0]] = a.ids ? a.ids[u] : u;
           if (a.k == 2) {
@@ -1371,12 +1399,16 @@ __global__ void __launch_bounds__(kWavesPerBlock * 64) gpm_list(ListArgs a) {
             o[a.out_col[1]] = a.ids ? a.ids[v] : v;
           }
         }
+        stage_n += (int32_t)__popcll(m);
+        if (stage_n > stage_rows - 64) list_flush(a, stage, stage_n);
       }
       continue;
     }
     for (int64_t t = t0; t < t1; ++t)
-      list_root(a.rp, a.col, a, uni(a.task_src[t]), uni(a.task_dst[t]), fb, st);
+      list_root(a.rp, a.col, a, uni(a.task_src[t]), uni(a.task_dst[t]), fb, st, stage, stage_n,
+                stage_rows);
   }
+  list_flush(a, stage, stage_n);
 }
 
 // ---------------------------------------------------------------------------

@@ -2224,24 +2224,26 @@ gpm_status gpm_list(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, in
     a.fbuf = s.d_fbuf;
     a.wave_stride = stride;
   }
+  // counters: [0] the matches found, [1] the task queue
   if (!c->d_list) HIP_TRY(c, hipMalloc((void**)&c->d_list, 2 * sizeof(unsigned long long)));
   if (!c->h_list)
     HIP_TRY(c, hipHostMalloc((void**)&c->h_list, 2 * sizeof(unsigned long long), hipHostMallocDefault));
-  a.cursor = c->d_list;
+  a.rows = c->d_list;
+  a.queue = c->d_list + 1;
   auto t0 = std::chrono::steady_clock::now();
   if (launch_fill_u64(c->d_list, 2, 0ull, s.stream))
     return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
   HIP_TRY(c, hipEventRecord(s.ev0, s.stream));
   if (launch_list(a, blocks, s.stream)) return fail(c, GPM_E_DEVICE, "listing kernel launch failed");
   HIP_TRY(c, hipEventRecord(s.ev1, s.stream));
-  HIP_TRY(c, hipMemcpyAsync(c->h_list, c->d_list, 2 * sizeof(unsigned long long),
+  HIP_TRY(c, hipMemcpyAsync(c->h_list, c->d_list, sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, s.stream));
   HIP_TRY(c, hipStreamSynchronize(s.stream));
   float ms = 0.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
   c->stats.kernel_ms = ms;
   c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  *count_out = (uint64_t)c->h_list[1];
+  *count_out = (uint64_t)c->h_list[0];
   return GPM_OK;
 }
 

@@ -319,6 +319,12 @@ def workload_rmat_s20(seed: int = 2) -> CSR:
     return rmat(20, 16, 0.57, 0.19, 0.19, seed)
 
 
+def workload_rmat_s16(seed: int = 1) -> CSR:
+    """R-MAT scale 16, edge factor 16, (a,b,c) = (0.57, 0.19, 0.19): the
+    listing workload (its 4-cliques fit a device buffer)."""
+    return rmat(16, 16, 0.57, 0.19, 0.19, seed)
+
+
 def workload_chung_lu_4m(seed: int = 3) -> CSR:
     """Chung-Lu, n = 4M, 60M edges (average degree 30), exponent 2.1."""
     return chung_lu(4_000_000, 30.0, 2.1, 1e5, 60_000_000, seed)

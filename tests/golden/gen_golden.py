@@ -23,6 +23,10 @@ WORKLOADS = {
                  [("triangle", lambda g: O.cliques(g, 3, 1)),
                   ("clique4", lambda g: O.cliques(g, 4, 1)),
                   ("clique5", lambda g: O.cliques(g, 5, 1))]),
+    # R-MAT scale 16, edge factor 16: the 4-clique listing workload
+    "rmat_s16": (synth.workload_rmat_s16,
+                 [("triangle", lambda g: O.cliques(g, 3, 1)),
+                  ("clique4", lambda g: O.cliques(g, 4, 1))]),
     # Chung-Lu n = 4M, 60M edges: edge-induced 4-cycle, diamond, tailed
     # triangle, induced 3-motifs
     "chung_lu_4m": (synth.workload_chung_lu_4m,

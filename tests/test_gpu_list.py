@@ -264,3 +264,22 @@ def test_list_errors(ctx):
             ctx.list(gid + 999, "triangle", torch.empty((4, 3), dtype=torch.int32, device="cuda"))
     finally:
         ctx.unload(gid)
+
+
+def test_list_cliques_with_large_roots(ctx, oracle):
+    """Roots with 70 out-neighbours (frontier sets of that size): K_{70,70}
+    plus sparse edges inside each side, few cliques."""
+    rng = np.random.default_rng(371)
+    a, b = synth.to_edge_list(synth.complete_bipartite(70, 70))
+    side = [(i, j) for i in range(70) for j in range(i + 1, 70) if rng.random() < 0.06]
+    us = list(a) + [i for i, _ in side] + [70 + i for i, _ in side[::2]]
+    vs = list(b) + [j for _, j in side] + [70 + j for _, j in side[::2]]
+    g = synth.from_edges(140, np.array(us), np.array(vs), "bipartite_plus_sides")
+    gid = ctx.load(g)
+    try:
+        for k in (3, 4):
+            check_against_oracle(ctx, oracle, g, gid, oracle.clique(k), V,
+                                 cap=oracle.cliques(g, k))
+        check_against_oracle(ctx, oracle, g, gid, "diamond", E)
+    finally:
+        ctx.unload(gid)
