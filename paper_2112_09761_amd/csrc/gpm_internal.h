@@ -170,6 +170,9 @@ struct ListArgs {
   unsigned long long* rows;    // matches found (rows claimed)
   int32_t* fbuf;             // frontier buffers: wave_stride words per wave
   int64_t wave_stride;
+  int32_t ordered;           // cliques on a DAG whose out-lists lie above their
+                             // vertex (u -> v iff u < v): a candidate of depth d
+                             // exceeds the vertex of depth d-1
 };
 
 // Host-side launchers (kernels.hip).  Return a hipError_t as int.

@@ -1223,6 +1223,7 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
 // coalesced copy.  (A claim per 64-candidate batch serialises the whole
 // grid on that one counter.)
 constexpr int kListStageWords = 2048;   // int32 words of staged rows per wave
+constexpr int kListProbeWords = 512;    // per wave: a leaf's probed list, when it fits
 
 // Write the wave's n staged rows (row-major, k words each) to the output and
 // empty the stage; rows at or beyond out_cap are counted and dropped.
@@ -1257,8 +1258,8 @@ __device__ __forceinline__ int32_t* stage_row(int32_t* stage, int32_t n, uint64_
 __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
                                           const int32_t* __restrict__ col, const ListArgs& a,
                                           const LevelPlan& L, const DfsState& st, int d,
-                                          int32_t* stage, int32_t& stage_n,
-                                          int32_t stage_rows) {
+                                          int32_t first_hint, int32_t* probe, int32_t* stage,
+                                          int32_t& stage_n, int32_t stage_rows) {
   int32_t bound = INT_MAX;
   for (int j = 0; j < d; ++j)
     if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
@@ -1277,19 +1278,43 @@ __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
       if (len < blen) { blen = len; base_i = i; base = col + rp[vj]; }
     }
   }
-  blen = uni(lower_bound(base, uni(blen), bound));
+  if (bound != INT_MAX) blen = uni(lower_bound(base, uni(blen), bound));
+  // ordered DAG: the leaf set lies in N+(v_{d-1}), above v_{d-1}; skip the
+  // sorted base's prefix up to it (first_hint >= 0: its length, known to
+  // the caller)
+  int32_t first = 0;
+  if (a.ordered) first = first_hint >= 0 ? first_hint : uni(lower_bound(base, blen, st.v[d - 1] + 1));
   // the caller's ids of the matched vertices, by depth
   int32_t mv[kMaxK - 1];
 #pragma unroll
   for (int j = 0; j < kMaxK - 1; ++j)
     mv[j] = j < d ? (a.ids ? a.ids[st.v[j]] : st.v[j]) : 0;
   const int l = lane_id();
-  for (int32_t ib = 0; ib < blen; ib += 64) {
+  // the first probed list, copied to the wave's LDS area when it fits: the
+  // lanes' binary searches then run in LDS instead of as chains of global loads
+  int q0 = -1;
+  for (int q = 0; q < L.n_int; ++q)
+    if (q != base_i) { q0 = q; break; }
+  const int32_t* N0 = nullptr;
+  int32_t n0 = 0;
+  if (q0 >= 0 && first < blen) {
+    const int32_t v0 = st.v[L.int_lv[q0]];
+    N0 = col + rp[v0];
+    n0 = (int32_t)(rp[v0 + 1] - rp[v0]);
+    if (n0 <= kListProbeWords) {
+      wave_sync_mem();  // the previous leaf's searches are done with the area
+      for (int32_t i = l; i < n0; i += 64) probe[i] = N0[i];
+      wave_sync_mem();
+      N0 = probe;
+    }
+  }
+  for (int32_t ib = first; ib < blen; ib += 64) {
     const int32_t i = ib + l;
     bool keep = i < blen;
     const int32_t x = keep ? base[i] : 0;
+    if (q0 >= 0 && keep) keep = member(N0, n0, x);
     for (int q = 0; q < L.n_int && keep; ++q) {
-      if (q == base_i) continue;
+      if (q == base_i || q == q0) continue;
       int32_t vj = st.v[L.int_lv[q]];
       keep = member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
     }
@@ -1318,14 +1343,15 @@ __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
 // the leaf depth emitted by list_leaf.
 __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                           const ListArgs& a, int32_t v0, int32_t v1, int32_t* fb,
-                          DfsState& st, int32_t* stage, int32_t& stage_n, int32_t stage_rows) {
+                          DfsState& st, int32_t* probe, int32_t* stage, int32_t& stage_n,
+                          int32_t stage_rows) {
   const Plan& P = a.plan;
   const int k = P.k;
   ElemCounter ec;  // not reported for listing
   st.v[0] = v0;
   st.v[1] = v1;
   if (k == 3) {
-    list_leaf(rp, col, a, P.lv[2], st, 2, stage, stage_n, stage_rows);
+    list_leaf(rp, col, a, P.lv[2], st, 2, -1, probe, stage, stage_n, stage_rows);
     return;
   }
   int d = 2;
@@ -1340,7 +1366,9 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
         const int32_t x = uni(st.set[d][i]);
         if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) continue;
         st.v[d] = x;
-        list_leaf(rp, col, a, P.lv[d + 1], st, d + 1, stage, stage_n, stage_rows);
+        // the leaf's base is this depth's set: its prefix up to x is [0, i]
+        const int32_t hint = P.lv[d + 1].base_buf == d ? i + 1 : -1;
+        list_leaf(rp, col, a, P.lv[d + 1], st, d + 1, hint, probe, stage, stage_n, stage_rows);
       }
       if (d == 2) break;
       --d;
@@ -1371,6 +1399,7 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
 // match (a vertex, or an edge taken once).
 __global__ void __launch_bounds__(kWavesPerBlock * 64) gpm_list(ListArgs a) {
   __shared__ int32_t list_stage[kWavesPerBlock][kListStageWords];
+  __shared__ int32_t list_probe[kWavesPerBlock][kListProbeWords];
   const int w = threadIdx.x >> 6;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + w;
   int32_t* fb = a.fbuf ? a.fbuf + gw * a.wave_stride : nullptr;
@@ -1405,8 +1434,8 @@ __global__ void __launch_bounds__(kWavesPerBlock * 64) gpm_list(ListArgs a) {
       continue;
     }
     for (int64_t t = t0; t < t1; ++t)
-      list_root(a.rp, a.col, a, uni(a.task_src[t]), uni(a.task_dst[t]), fb, st, stage, stage_n,
-                stage_rows);
+      list_root(a.rp, a.col, a, uni(a.task_src[t]), uni(a.task_dst[t]), fb, st, list_probe[w],
+                stage, stage_n, stage_rows);
   }
   list_flush(a, stage, stage_n);
 }

@@ -2151,6 +2151,7 @@ gpm_status gpm_list(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, in
     if (st) return st;
     V = &g.dag;
     a.ids = g.dag_only ? nullptr : g.ren_ids;
+    a.ordered = g.dag_ordered ? 1 : 0;
     a.task_src = g.dag.src;
     a.task_dst = g.dag.col;
     a.n_tasks = g.dag.nnz;
