@@ -1250,6 +1250,90 @@ __device__ __forceinline__ int32_t* stage_row(int32_t* stage, int32_t n, uint64_
   return stage + (n + (int32_t)lanes_below(m)) * k;
 }
 
+// The first probed list of a listing depth (index q0 among the lists to
+// intersect, -1 if none), copied to the wave's LDS area when it fits so the
+// lanes' binary searches run in LDS instead of as chains of global loads.
+__device__ __forceinline__ const int32_t* list_probe_list(const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const LevelPlan& L,
+                                                          const DfsState& st, int base_i,
+                                                          int32_t* probe, int& q0, int32_t& n0) {
+  q0 = -1;
+  n0 = 0;
+  for (int q = 0; q < L.n_int; ++q)
+    if (q != base_i) { q0 = q; break; }
+  if (q0 < 0) return nullptr;
+  const int32_t v = st.v[L.int_lv[q0]];
+  const int32_t* N = col + rp[v];
+  n0 = (int32_t)(rp[v + 1] - rp[v]);
+  if (n0 > kListProbeWords) return N;
+  wave_sync_mem();  // earlier searches are done with the area
+  for (int32_t i = lane_id(); i < n0; i += 64) probe[i] = N[i];
+  wave_sync_mem();
+  return probe;
+}
+
+// A stored (or sliced) depth d < k-1 of a listing walk: the candidate set as
+// dfs_level<true> forms it, with the leaf's two latency cuts (no search for a
+// bound the plan does not have; the first probed list searched in LDS).
+__device__ __forceinline__ int32_t list_level(const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col,
+                                              const LevelPlan& L, DfsState& st, int d,
+                                              int32_t* out, int32_t* probe) {
+  int32_t bound = INT_MAX;
+  for (int j = 0; j < d; ++j)
+    if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
+  const int32_t* base;
+  int32_t blen;
+  int base_i = -1;
+  if (L.base_buf >= 0) {
+    base = st.set[L.base_buf];
+    blen = st.sz[L.base_buf];
+  } else {
+    blen = INT_MAX;
+    base = nullptr;
+    for (int i = 0; i < L.n_int; ++i) {
+      int32_t vj = st.v[L.int_lv[i]];
+      int32_t len = (int32_t)(rp[vj + 1] - rp[vj]);
+      if (len < blen) { blen = len; base_i = i; base = col + rp[vj]; }
+    }
+  }
+  if (bound != INT_MAX) blen = uni(lower_bound(base, uni(blen), bound));
+  if (L.flags & kLvSlice) {
+    st.set[d] = base;
+    return blen;
+  }
+  int q0;
+  int32_t n0;
+  const int32_t* N0 = blen > 0 ? list_probe_list(rp, col, L, st, base_i, probe, q0, n0) : nullptr;
+  if (blen <= 0) q0 = -1;
+  const int l = lane_id();
+  int32_t total = 0;
+  for (int32_t ib = 0; ib < blen; ib += 64) {
+    const int32_t i = ib + l;
+    bool keep = i < blen;
+    const int32_t x = keep ? base[i] : 0;
+    if (q0 >= 0 && keep) keep = member(N0, n0, x);
+    for (int q = 0; q < L.n_int && keep; ++q) {
+      if (q == base_i || q == q0) continue;
+      int32_t vj = st.v[L.int_lv[q]];
+      keep = member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int q = 0; q < L.n_sub && keep; ++q) {
+      int32_t vj = st.v[L.sub_lv[q]];
+      keep = !member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+    }
+    for (int j = 0; j < d && keep; ++j)
+      if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
+    const uint64_t m = wave_ballot(keep);
+    if (keep) out[total + (int32_t)lanes_below(m)] = x;
+    total += (int32_t)__popcll(m);
+  }
+  wave_sync_mem();
+  st.set[d] = out;
+  return total;
+}
+
 // The leaf depth d = k-1 of a listing walk.  Its candidate set is formed as
 // dfs_level forms it (bounded base, membership probes, subtractions in
 // vertex-induced mode, explicit exclusion of matched vertices), one candidate
@@ -1293,21 +1377,9 @@ __device__ __forceinline__ void list_leaf(const int64_t* __restrict__ rp,
   // the first probed list, copied to the wave's LDS area when it fits: the
   // lanes' binary searches then run in LDS instead of as chains of global loads
   int q0 = -1;
-  for (int q = 0; q < L.n_int; ++q)
-    if (q != base_i) { q0 = q; break; }
-  const int32_t* N0 = nullptr;
   int32_t n0 = 0;
-  if (q0 >= 0 && first < blen) {
-    const int32_t v0 = st.v[L.int_lv[q0]];
-    N0 = col + rp[v0];
-    n0 = (int32_t)(rp[v0 + 1] - rp[v0]);
-    if (n0 <= kListProbeWords) {
-      wave_sync_mem();  // the previous leaf's searches are done with the area
-      for (int32_t i = l; i < n0; i += 64) probe[i] = N0[i];
-      wave_sync_mem();
-      N0 = probe;
-    }
-  }
+  const int32_t* N0 = nullptr;
+  if (first < blen) N0 = list_probe_list(rp, col, L, st, base_i, probe, q0, n0);
   for (int32_t ib = first; ib < blen; ib += 64) {
     const int32_t i = ib + l;
     bool keep = i < blen;
@@ -1347,7 +1419,6 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
                           int32_t stage_rows) {
   const Plan& P = a.plan;
   const int k = P.k;
-  ElemCounter ec;  // not reported for listing
   st.v[0] = v0;
   st.v[1] = v1;
   if (k == 3) {
@@ -1357,7 +1428,7 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
   int d = 2;
   {
     int32_t* out = fb + (size_t)(P.store_slot[2] < 0 ? 0 : P.store_slot[2]) * a.cap;
-    st.sz[2] = uni(dfs_level<true, false>(rp, col, P.lv[2], st, 2, out, ec));
+    st.sz[2] = uni(list_level(rp, col, P.lv[2], st, 2, out, probe));
     st.ix[2] = 0;
   }
   for (;;) {
@@ -1389,7 +1460,7 @@ __device__ void list_root(const int64_t* __restrict__ rp, const int32_t* __restr
     st.v[d] = x;
     ++d;
     int32_t* out = fb + (size_t)(P.store_slot[d] < 0 ? 0 : P.store_slot[d]) * a.cap;
-    st.sz[d] = uni(dfs_level<true, false>(rp, col, P.lv[d], st, d, out, ec));
+    st.sz[d] = uni(list_level(rp, col, P.lv[d], st, d, out, probe));
     st.ix[d] = 0;
   }
 }
