@@ -31,8 +31,8 @@ WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
 # for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
 # the kernel sources they were taken on (and that launch) only; else null.
-TRAFFIC = {"sources_sha256": "3dd68a0b0870d04c53066acc8c87d68cc3be7d759d5326962a572d5898a0b81e",
-           "k": 5, "kinds": 1 << 7, "fetch_kib": 1844383.0, "write_kib": 866.2,
+TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856ae6169957da11ce16fb",
+           "k": 5, "kinds": 1 << 7, "fetch_kib": 1847122.3, "write_kib": 866.2,
            "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
 
@@ -89,8 +89,8 @@ def measured_traffic(k, kinds):
 
 # gpm_list on the listing workload: the same two counter passes (KiB per
 # dispatch), valid for the sources they were taken on
-LIST_TRAFFIC = {"sources_sha256": "3dd68a0b0870d04c53066acc8c87d68cc3be7d759d5326962a572d5898a0b81e",
-                "fetch_kib": 154205.3, "write_kib": 5026110.5,
+LIST_TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856ae6169957da11ce16fb",
+                "fetch_kib": 160388.1, "write_kib": 5050520.3,
                 "fetch_factor": 2.0, "write_factor": 1.0}
 
 
