@@ -138,6 +138,21 @@ def test_list_six_vertex_pattern_and_cliques_to_eight(ctx, oracle):
         ctx.unload(gid)
 
 
+def test_list_random_patterns_seven_eight(ctx, oracle):
+    from test_gpu_parity import random_pattern
+    for seed in range(2):
+        rng = np.random.default_rng(500 + seed)
+        g = synth.erdos_renyi(30, 0.3, 600 + seed)
+        gid = ctx.load(g)
+        try:
+            for k in (7, 8):
+                pat = random_pattern(rng, k)
+                for mode in (V, E):
+                    check_against_oracle(ctx, oracle, g, gid, pat, mode)
+        finally:
+            ctx.unload(gid)
+
+
 def test_list_without_relabelling(ctx, oracle):
     g = synth.rmat(8, 8, seed=321)
     gid = ctx.load(g)

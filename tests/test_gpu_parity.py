@@ -134,6 +134,24 @@ def test_random_patterns(ctx, oracle, seed):
         ctx.unload(gid)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_random_patterns_seven_eight(ctx, oracle, seed):
+    """Random connected 7- and 8-vertex patterns (the largest plans: seven
+    levels, up to six stored depths)."""
+    rng = np.random.default_rng(500 + seed)
+    g = synth.erdos_renyi(30, 0.3, 600 + seed)
+    gid = ctx.load(g)
+    try:
+        for k in (7, 8):
+            pat = random_pattern(rng, k)
+            for mode in (V, E):
+                got = ctx.count(gid, pat, mode)
+                exp = oracle.count_embed(g, pat, mode == V)
+                assert got == exp, (pat, mode, got, exp)
+    finally:
+        ctx.unload(gid)
+
+
 @pytest.mark.parametrize("k", [3, 4, 5, 6, 7, 8])
 def test_cliques_multipartite(ctx, k):
     import itertools
