@@ -298,3 +298,41 @@ def test_list_cliques_with_large_roots(ctx, oracle):
         check_against_oracle(ctx, oracle, g, gid, "diamond", E)
     finally:
         ctx.unload(gid)
+
+
+def test_list_full_size_workload(ctx):
+    """The listing workload at full size (R-MAT scale 16, edge factor 16:
+    293M 4-cliques, 4.7 GB of rows), in the launch bench.py times: the count
+    equals the stored oracle value, every row has 4 distinct vertices, no two
+    rows share a vertex set (all rows, sorted on the device), and sampled rows
+    are 4-cliques."""
+    import json
+    import os
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "rmat_s16_oracle.json")))
+    g = synth.workload_rmat_s16()
+    assert g.sha256() == gold["sha256"]
+    cnt = gold["counts"]["clique4"]
+    gid = ctx.load(g)
+    try:
+        buf = torch.empty((cnt, 4), dtype=torch.int32, device="cuda")
+        total = ctx.list(gid, "clique4", buf)
+        assert total == cnt
+        rows = torch.sort(buf, dim=1).values
+        del buf
+        assert bool((rows[:, 1:] != rows[:, :-1]).all()), "a row repeats a vertex"
+        assert g.n <= 1 << 16
+        r64 = rows.to(torch.int64)
+        key = (r64[:, 0] << 48) | (r64[:, 1] << 32) | (r64[:, 2] << 16) | r64[:, 3]
+        del r64
+        key = torch.sort(key).values
+        assert bool((key[1:] != key[:-1]).all()), "a 4-clique listed twice"
+        del key
+        rng = np.random.default_rng(13)
+        pick = torch.from_numpy(rng.choice(cnt, size=5000, replace=False)).cuda()
+        sample = rows[pick].cpu().numpy().astype(np.int64)
+        for a, b in itertools.combinations(range(4), 2):
+            assert has_edges(g, sample[:, a], sample[:, b]).all()
+    finally:
+        ctx.unload(gid)
