@@ -57,7 +57,7 @@ enum { GPM_VERTEX_INDUCED = 0, GPM_EDGE_INDUCED = 1 };
 enum {
     GPM_CSR_SYMMETRIC = 1,   /* every edge stored in both directions        */
     GPM_CSR_DAG = 2,         /* already oriented (each edge once): cliques
-                                only (orientation, Sec. 3, graph loader)     */
+                                only (orientation, Sec. 4.2, graph loader)   */
     GPM_PTRS_DEVICE = 4,     /* row_ptr / col are device pointers on the
                                 context's device (e.g. torch data_ptr())     */
     GPM_VALIDATE = 8         /* also check symmetry, O(m log d) on the host  */
@@ -200,7 +200,7 @@ gpm_status gpm_set_option(gpm_ctx *ctx, const char *key, int64_t value);
 gpm_status gpm_get_stats(const gpm_ctx *ctx, gpm_stats *out);
 
 /* ---------------------------------------------------------------------- */
-/* graphs (graph loader and preprocessor, Sec. 3)                          */
+/* graphs (graph loader and preprocessor, Sec. 4.2)                        */
 /* ---------------------------------------------------------------------- */
 
 /* Load a data graph in CSR form: row_ptr[n+1] (int64, row_ptr[0] = 0,
@@ -282,7 +282,7 @@ gpm_status gpm_frontier_waves(int64_t free_bytes, int32_t x_levels,
 
 /* Exact number of distinct matches of `pattern` in graph `graph_id`
  * (each subgraph once: completeness and uniqueness, Sec. 2.1), vertex- or
- * edge-induced (`mode`).  Cliques run on the degree-oriented DAG (Sec. 3,
+ * edge-induced (`mode`).  Cliques run on the degree-oriented DAG (Sec. 4.2,
  * orientation); other patterns on the symmetric graph with the symmetry
  * order of Sec. 2.2.  k = 1 returns n, k = 2 returns m, n < k returns 0.
  * Blocks until the count is on the host (the context's stream is
@@ -349,23 +349,38 @@ typedef struct {
 gpm_status gpm_count_batch(gpm_ctx *ctx, int32_t nq, const gpm_query *queries,
                            uint64_t *outs);
 
-/* Serving: submit one query without blocking.  The query is admitted when a
- * launch slot is free and its frontier memory fits the budget; launches on
- * different slots overlap on the device.  Queries whose last run alone took
- * at most "serve_light_ms" (default 50) are light: light queries admitted
- * together share one persistent launch (at most "max_batch").  Other queries
- * (heavy, or not yet measured) run alone and hold at most half of the slots,
- * so light queries keep slots of their own.  GPM_E_BUSY when the pending list
- * is full.  *ticket_out identifies the query for gpm_poll / gpm_wait. */
+/* Serving: submit one query without blocking.  The query is checked here
+ * (graph id, kind, mode, pattern, and a pattern the graph can run) and gets
+ * no ticket when a check fails: GPM_E_INVAL, GPM_E_PATTERN or
+ * GPM_E_UNSUPPORTED, as gpm_count would return; GPM_E_BUSY when the pending
+ * list is full ("max_pending").  An accepted query is admitted when a launch
+ * slot is free and its frontier memory fits what the running launches leave
+ * of the budget (adaptive buffering, Sec. 7.2 (3)); queries are admitted in
+ * arrival order, and one that does not fit beside the running launches
+ * waits, first in line, until they finish.  Launches on different slots
+ * overlap on the device.  Queries whose last run alone took at most
+ * "serve_light_ms" (default 50) are light: light queries admitted together
+ * share one persistent launch (at most "max_batch").  Other queries (heavy,
+ * or not yet measured) run alone and hold at most half of the slots, so
+ * light queries keep slots of their own.  *ticket_out identifies the query
+ * for gpm_poll / gpm_wait until its result is collected. */
 gpm_status gpm_submit(gpm_ctx *ctx, const gpm_query *query, int64_t *ticket_out);
 
-/* Progress the serving loop; *done_out = 1 when the ticket's result is
- * ready, in which case counts_out[6] (host, caller-owned) receives it and
- * the ticket is released. */
+/* Progress the serving loop and look at one ticket.  *done_out = 0: the query
+ * is still pending or running (return GPM_OK), or the call itself failed
+ * (GPM_E_INVAL for a ticket that was never issued or was already collected;
+ * GPM_E_DEVICE).  *done_out = 1: the query completed and the ticket is
+ * released; the return value is the query's own status -- GPM_OK with
+ * counts_out[6] (host, caller-owned; 1 value for COUNT, 2 or 6 for MOTIFS,
+ * the rest zero) written, or the error that stopped it (GPM_E_NOMEM when its
+ * buffers do not fit the whole memory budget, GPM_E_DEVICE, ...; counts_out
+ * untouched, gpm_last_error() describes it). */
 gpm_status gpm_poll(gpm_ctx *ctx, int64_t ticket, int *done_out,
                     uint64_t *counts_out);
 
-/* Block until the ticket completes or timeout_ns passes (GPM_E_TIMEOUT). */
+/* Block until the ticket completes, then return as gpm_poll does for a
+ * completed ticket; GPM_E_TIMEOUT (query still live) once timeout_ns passes
+ * (timeout_ns < 0: no limit); GPM_E_INVAL at once for an unknown ticket. */
 gpm_status gpm_wait(gpm_ctx *ctx, int64_t ticket, int64_t timeout_ns,
                     uint64_t *counts_out);
 

@@ -26,9 +26,11 @@
  *   orc_triangles       triangles with marker arrays on an oriented graph,
  *                       also per-vertex and per-edge triangle counts;
  *   orc_cliques         k-cliques by recursive marker-array enumeration on
- *                       an oriented graph (orientation: paper Sec. 3,
+ *                       an oriented graph (orientation: paper Sec. 4.2,
  *                       "Graph Loader and Preprocessor");
  *   orc_cycle4          4-cycles by codegree (wedge-pair) counting;
+ *   orc_cycle4_trace    4-cycles from tr(A^4), the closed 4-walks, with the
+ *                       edge-retracing walks removed (no ranking at all);
  *   orc_nonind4         the six non-induced 4-vertex counts from local
  *                       triangle and degree terms (the counting-only
  *                       decomposition of Sec. 5.4 (1), Alg. 3, for diamond);
@@ -415,7 +417,7 @@ int orc_list_embed(int64_t n, const int64_t *rp, const int32_t *col,
 }
 
 /* ------------------------------------------------------------------ */
-/* orientation (paper Sec. 3, "Graph Loader and Preprocessor"):         */
+/* orientation (paper Sec. 4.2, "Graph Loader and Preprocessor"):       */
 /* keep u->v when u precedes v; by id (order 0) or by (degree, id)     */
 /* (order 1).  The oriented lists keep the ascending id order.          */
 /* ------------------------------------------------------------------ */
@@ -709,6 +711,70 @@ int orc_cycle4(int64_t n, const int64_t *rp, const int32_t *col, uint64_t *out)
 }
 
 /* ------------------------------------------------------------------ */
+/* 4-cycles from the trace of A^4 (no ranking, no orientation)          */
+/* ------------------------------------------------------------------ */
+/*
+ * tr(A^4) counts closed walks of length 4.  A 4-cycle gives 8 of them (4
+ * starting vertices x 2 directions); every other closed 4-walk retraces an
+ * edge, and there are 2 sum d^2 - sum d of those (v-u-v-u'-v: d_v^2 per
+ * start v; v-u-w-u-v with w != v: sum over u in N(v) of d_u - 1).  So
+ *   C4 = (tr(A^4) - 2 sum d^2 + sum d) / 8,
+ * and tr(A^4) = sum over (v, w) of ((A^2)_vw)^2, where (A^2)_vw is the
+ * number of 2-walks v-u-w (d_v when w = v).  Row v of A^2 is tallied in
+ * cnt[] by walking v-u-w over every u and w, then squared and summed.
+ */
+int orc_cycle4_trace(int64_t n, const int64_t *rp, const int32_t *col, uint64_t *out)
+{
+    static u128 acc[MAXT];
+    int nt = omp_get_max_threads();
+    if (nt > MAXT) nt = MAXT;
+    memset(acc, 0, sizeof acc);
+    int fail = 0;
+#pragma omp parallel num_threads(nt)
+    {
+        int t = omp_get_thread_num();
+        uint32_t *cnt = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+        int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+        if (!cnt || !touched) {
+#pragma omp atomic write
+            fail = 1;
+        }
+        u128 local = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < n; v++) {
+            if (!cnt || !touched) continue;
+            int64_t nt_ = 0;
+            for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+                int64_t u = col[e];
+                for (int64_t f = rp[u]; f < rp[u + 1]; f++) {
+                    int64_t w = col[f];
+                    if (cnt[w]++ == 0) touched[nt_++] = (int32_t)w;
+                }
+            }
+            for (int64_t i = 0; i < nt_; i++) {
+                u128 c = cnt[touched[i]];
+                local += c * c;
+                cnt[touched[i]] = 0;
+            }
+        }
+        acc[t] = local;
+        free(cnt); free(touched);
+    }
+    if (fail) return ORC_ENOMEM;
+    u128 tr4 = 0, sd2 = 0, sd = 0;
+    for (int t = 0; t < nt; t++) tr4 += acc[t];
+    for (int64_t v = 0; v < n; v++) {
+        u128 d = (u128)(rp[v + 1] - rp[v]);
+        sd2 += d * d;
+        sd += d;
+    }
+    u128 c4 = (tr4 + sd - 2 * sd2) / 8;
+    if (!fits64(c4)) return ORC_EOVERFLOW;
+    *out = (uint64_t)c4;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* O4: non-induced (= edge-induced) 4-vertex counts                     */
 /* ------------------------------------------------------------------ */
 /*
@@ -725,8 +791,8 @@ int orc_cycle4(int64_t n, const int64_t *rp, const int32_t *col, uint64_t *out)
  *                                              3-cycle and are removed)
  *   N_C4 = codegree count;  N_K4 = k-clique enumeration.
  */
-int orc_nonind4(int64_t n, const int64_t *rp, const int32_t *col, int order,
-                uint64_t out[6])
+static int nonind4_local_terms(int64_t n, const int64_t *rp, const int32_t *col, int order,
+                               u128 *nd, u128 *ntt, u128 *ns3, u128 *np4)
 {
     int64_t nnz = rp[n];
     uint64_t *tv = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)n + 1));
@@ -735,22 +801,31 @@ int orc_nonind4(int64_t n, const int64_t *rp, const int32_t *col, int order,
     uint64_t T;
     int st = orc_triangles(n, rp, col, order, &T, tv, te);
     if (st) { free(tv); free(te); return st; }
-    u128 nd = 0, ntt = 0, ns3 = 0, np4 = 0;
+    *nd = 0; *ntt = 0; *ns3 = 0; *np4 = 0;
     for (int64_t u = 0; u < n; u++) {
         u128 d = (u128)(rp[u + 1] - rp[u]);
-        if (d >= 3) ns3 += d * (d - 1) * (d - 2) / 6;
-        if (d >= 2) ntt += (u128)tv[u] * (d - 2);
+        if (d >= 3) *ns3 += d * (d - 1) * (d - 2) / 6;
+        if (d >= 2) *ntt += (u128)tv[u] * (d - 2);
         for (int64_t e = rp[u]; e < rp[u + 1]; e++) {
             int64_t v = col[e];
             if (v <= u) continue;           /* each undirected edge once */
             u128 dv = (u128)(rp[v + 1] - rp[v]);
             u128 t = te[e];
-            if (t >= 2) nd += t * (t - 1) / 2;
-            np4 += (d - 1) * (dv - 1);
+            if (t >= 2) *nd += t * (t - 1) / 2;
+            *np4 += (d - 1) * (dv - 1);
         }
     }
-    np4 -= (u128)3 * T;
+    *np4 -= (u128)3 * T;
     free(tv); free(te);
+    return ORC_OK;
+}
+
+int orc_nonind4(int64_t n, const int64_t *rp, const int32_t *col, int order,
+                uint64_t out[6])
+{
+    u128 nd, ntt, ns3, np4;
+    int st = nonind4_local_terms(n, rp, col, order, &nd, &ntt, &ns3, &np4);
+    if (st) return st;
     uint64_t c4, k4;
     st = orc_cycle4(n, rp, col, &c4);
     if (st) return st;
@@ -764,6 +839,24 @@ int orc_nonind4(int64_t n, const int64_t *rp, const int32_t *col, int order,
     out[3] = (uint64_t)ntt;
     out[4] = (uint64_t)nd;
     out[5] = k4;
+    return ORC_OK;
+}
+
+/* The non-induced counts that need only local triangle and degree terms:
+ * out = [path4, star3, tailed_triangle, diamond] (no 4-cycle or 4-clique
+ * enumeration; the same terms as orc_nonind4). */
+int orc_nonind4_local(int64_t n, const int64_t *rp, const int32_t *col, int order,
+                      uint64_t out[4])
+{
+    u128 nd, ntt, ns3, np4;
+    int st = nonind4_local_terms(n, rp, col, order, &nd, &ntt, &ns3, &np4);
+    if (st) return st;
+    if (!fits64(nd) || !fits64(ntt) || !fits64(ns3) || !fits64(np4))
+        return ORC_EOVERFLOW;
+    out[0] = (uint64_t)np4;
+    out[1] = (uint64_t)ns3;
+    out[2] = (uint64_t)ntt;
+    out[3] = (uint64_t)nd;
     return ORC_OK;
 }
 

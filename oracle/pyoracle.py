@@ -70,7 +70,8 @@ def _declare(L):
     L.orc_cliques.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_int,
                               ctypes.c_int, P_U64]
     L.orc_cycle4.argtypes = [ctypes.c_int64, P_I64, P_I32, P_U64]
-    for name in ("orc_nonind4", "orc_motifs3", "orc_motifs4"):
+    L.orc_cycle4_trace.argtypes = [ctypes.c_int64, P_I64, P_I32, P_U64]
+    for name in ("orc_nonind4", "orc_motifs3", "orc_motifs4", "orc_nonind4_local"):
         getattr(L, name).argtypes = [ctypes.c_int64, P_I64, P_I32,
                                      ctypes.c_int, P_U64]
     L.orc_num_threads.restype = ctypes.c_int
@@ -177,6 +178,14 @@ def cycle4(g) -> int:
     return out.value
 
 
+def cycle4_trace(g) -> int:
+    """4-cycles from tr(A^4) (closed 4-walks), a route with no ranking."""
+    n, rp, col, prp, pcol = _csr(g)
+    out = ctypes.c_uint64()
+    _check(lib().orc_cycle4_trace(n, prp, pcol, ctypes.byref(out)))
+    return out.value
+
+
 def _vec(name, g, order, size):
     n, rp, col, prp, pcol = _csr(g)
     out = np.zeros(size, dtype=np.uint64)
@@ -187,6 +196,12 @@ def _vec(name, g, order, size):
 def nonind4(g, order: int = 1):
     """[path4, star3, cycle4, tailed_triangle, diamond, clique4], non-induced."""
     return _vec("orc_nonind4", g, order, 6)
+
+
+def nonind4_local(g, order: int = 1):
+    """[path4, star3, tailed_triangle, diamond], non-induced (the counts that
+    need only triangle and degree terms)."""
+    return _vec("orc_nonind4_local", g, order, 4)
 
 
 def motifs3(g, order: int = 1):

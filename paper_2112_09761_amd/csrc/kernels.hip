@@ -52,6 +52,16 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
   return x;
 }
 
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int64_t y = __shfl_up(x, off, 64);
+    if (l >= off) x += y;
+  }
+  return x;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -86,8 +96,8 @@ __device__ __forceinline__ bool member(const T* a, int32_t n, int32_t key) {
 }
 
 // First index i in [0, n) with a[i] > key.
-template <typename T>
-__device__ __forceinline__ int32_t upper_bound(const T* a, int32_t n, int32_t key) {
+template <typename T, typename K>
+__device__ __forceinline__ int32_t upper_bound(const T* a, int32_t n, K key) {
   if (n <= 0) return 0;
   int32_t base = 0;
   while (n > 1) {
@@ -145,40 +155,41 @@ __device__ __forceinline__ uint32_t intersect_count(const TA* A, int32_t na, con
 }
 
 // ---------------------------------------------------------------------------
-// k-clique on the oriented DAG (Sec. 3 orientation; Alg. 1 with every level
+// k-clique on the oriented DAG (Sec. 4.2 orientation; Alg. 1 with every level
 // an intersection).  Sets F_d of candidates for v_d; the last two vertices
 // are counted together as the number of DAG edges inside F_{k-2}.
 // ---------------------------------------------------------------------------
 
-// Sum over w in F of |F ∩ N+(w)|.  P is scratch of s + 1 ints.
+// Sum over w in F of |F ∩ N+(w)|.  P is scratch of s + 1 int64 (the prefix of
+// the out-degrees over F can pass 2^31 on a caller's DAG with large lists).
 template <bool CE, typename TF, typename TP>
 __device__ __forceinline__ uint64_t clique_leaf(const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col,
                                                 const TF* F, int32_t s, TP* P,
                                                 ElemCounter& ec) {
   const int l = lane_id();
-  int32_t running = 0;
+  int64_t running = 0;
   for (int32_t ib = 0; ib < s; ib += 64) {
     int32_t i = ib + l;
-    int32_t d = 0;
+    int64_t d = 0;
     if (i < s) {
       int32_t w = F[i];
-      d = (int32_t)(rp[w + 1] - rp[w]);
+      d = rp[w + 1] - rp[w];
     }
-    int32_t inc = wave_incl_scan(d);
+    int64_t inc = wave_incl_scan64(d);
     if (i < s) P[i + 1] = running + inc;
     running += __shfl(inc, 63, 64);
   }
   if (l == 0) P[0] = 0;
   wave_sync_mem();
-  running = uni(running);
+  running = uni64(running);
   if (CE) {
     ec.elems += (uint64_t)s * (uint64_t)s + (uint64_t)running;
     ec.fetches += (uint64_t)s;
   }
   uint64_t c = 0;
-  for (int32_t tb = 0; tb < running; tb += 64) {
-    int32_t t = tb + l;
+  for (int64_t tb = 0; tb < running; tb += 64) {
+    int64_t t = tb + l;
     if (t < running) {
       // owner i: P[i] <= t < P[i+1]
       int32_t i = upper_bound(P + 1, s, t);
@@ -191,13 +202,13 @@ __device__ __forceinline__ uint64_t clique_leaf(const int64_t* __restrict__ rp,
 }
 
 // Count k-cliques (k >= 3) whose first two vertices are the DAG edge u->v.
-// U = N+(u) (LDS-staged or global), bufs: (k-3) sets of cap ints, P: cap+1,
-// st: 2*kMaxK ints of wave state.
+// U = N+(u) (LDS-staged or global), bufs: (k-3) sets of cap ints, P: cap+1
+// int64, st: 2*kMaxK ints of wave state.
 template <bool CE, typename TU, typename TB>
 __device__ __forceinline__ uint64_t clique_edge(const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col, int k,
                                                 const TU* U, int32_t du, int32_t v,
-                                                TB* bufs, TB* P, int32_t cap,
+                                                TB* bufs, int64_t* P, int32_t cap,
                                                 int32_t* st, ElemCounter& ec) {
   const int32_t* Nv = col + rp[v];
   const int32_t dv = uni((int32_t)(rp[v + 1] - rp[v]));
@@ -1634,10 +1645,10 @@ gpm_persistent(KernelArgs a) {
         int32_t v = uni(J.task_dst[t]);
         int32_t du = uni((int32_t)(rp[u + 1] - rp[u]));
         if (J.lds_ok && du <= a.lds_cap) {
-          // LDS tile: U | F_2 .. F_{k-2} | P
+          // LDS tile: U | F_2 .. F_{k-2} | (pad to 8 B) | P (int64)
           int32_t* U = my;
           int32_t* bufs = my + a.lds_cap;
-          int32_t* P = bufs + (size_t)(k - 3 > 0 ? k - 3 : 0) * a.lds_cap;
+          int64_t* P = (int64_t*)(my + ((a.lds_cap + (size_t)(k - 3 > 0 ? k - 3 : 0) * a.lds_cap + 1) & ~(size_t)1));
           if (u != cached_u) {
             const int32_t* Nu = col + rp[u];
             for (int32_t i = lane_id(); i < du; i += 64) U[i] = Nu[i];
@@ -1649,7 +1660,7 @@ gpm_persistent(KernelArgs a) {
         } else {
           const int32_t* U = col + rp[u];
           int32_t* bufs = fb;
-          int32_t* P = fb + (size_t)(k - 3 > 0 ? k - 3 : 0) * J.cap;
+          int64_t* P = (int64_t*)(fb + (((size_t)(k - 3 > 0 ? k - 3 : 0) * J.cap + 1) & ~(size_t)1));
           acc[0] += clique_edge<CE>(rp, col, k, U, du, v, bufs, P, J.cap, st_words, ec);
         }
       }

@@ -130,7 +130,7 @@ int build_plan(const gpm_pattern& p, int mode, bool on_dag, HostPlan* out, std::
   for (int d = 0; d < kMaxK; ++d) P.store_slot[d] = -1;
 
   if (on_dag) {
-    // Cliques on the oriented DAG (Sec. 3): the orientation already breaks
+    // Cliques on the oriented DAG (Sec. 4.2, graph preprocessing): the orientation already breaks
     // every symmetry, so there are no bounds; depth l intersects the set of
     // depth l-1 with N+(v_{l-1}).
     if (!hp.clique) {

@@ -1,6 +1,6 @@
 // Host runtime of libgpm: the C ABI of include/gpm.h.
 //
-// Graph loader and preprocessor (Sec. 3): validation, degree orientation for
+// Graph loader and preprocessor (Sec. 4.2, System Interface): validation, degree orientation for
 // cliques, root task lists (edge list halved when the plan orders v1 < v0,
 // Sec. 7.2 (2)).  Runtime (Sec. 7): frontier buffers sized to the device
 // memory budget (adaptive buffering, Sec. 7.2 (3)), persistent launches fed
@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -19,6 +20,7 @@
 #include <memory>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/gpm.h"
@@ -138,6 +140,13 @@ struct Pending {
   int64_t ticket;
 };
 
+// A completed served query: its status and, on GPM_OK, its results.
+struct Done {
+  gpm_status st = GPM_OK;
+  std::string err;
+  std::array<uint64_t, 6> r{};
+};
+
 }  // namespace
 
 struct gpm_ctx {
@@ -169,7 +178,8 @@ struct gpm_ctx {
   Slot slots[kMaxSlots + 1];  // [0]: synchronous calls on the user stream
   // serving
   std::deque<Pending> pending;
-  std::unordered_map<int64_t, std::array<uint64_t, 6>> done;
+  std::unordered_map<int64_t, Done> done;
+  std::unordered_set<int64_t> issued;   // tickets not yet collected
   std::unordered_map<std::string, double> qcost;  // kernel ms of queries run alone
   int64_t opt_serve_light_ms = 50;
   int64_t next_ticket = 1;
@@ -271,7 +281,7 @@ static gpm_status upload_view(gpm_ctx* c, const HostCSR& h, bool with_src, Graph
 
 static gpm_status ensure_ren(gpm_ctx* c, Graph& g);
 
-// Orientation by (degree, id) (Sec. 3 "Graph Loader and Preprocessor":
+// Orientation by (degree, id) (Sec. 4.2, "Graph Loader and Preprocessor":
 // orientation halves the edges and shrinks the maximum degree).
 static gpm_status ensure_dag(gpm_ctx* c, Graph& g) {
   if (g.dag_ready) return GPM_OK;
@@ -450,7 +460,7 @@ static gpm_status lower_edges(gpm_ctx* c, const HostCSR& h, int32_t** src, int32
   return GPM_OK;
 }
 
-// Relabel by ascending (degree, id) rank (Sec. 3: the preprocessor may sort
+// Relabel by ascending (degree, id) rank (Sec. 4.2: the preprocessor may sort
 // and rename vertices by degree).  Counts are invariant under relabelling.
 static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
   if (g.ren_ready) return GPM_OK;
@@ -1215,7 +1225,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     jobs[i].slot = perm[i];  // result slot = the job's original index
   }
 
-  // LDS tile of the clique kernel: U | F_2 .. F_{k-2} | P per wave
+  // LDS tile of the clique kernel: U | F_2 .. F_{k-2} | pad | P (int64) per wave
   bool any_clique = false;
   int kmax = 3;
   for (int i = 0; i < nj; ++i)
@@ -1226,7 +1236,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   int32_t lcap = 0, lds_words = 0;
   if (any_clique) {
     auto words = [&](int32_t cap) {
-      return (int32_t)align_up((size_t)cap * (1 + std::max(kmax - 3, 0)) + cap + 1, 4);
+      return (int32_t)align_up((size_t)cap * (1 + std::max(kmax - 3, 0)) + 1 + 2 * ((size_t)cap + 1), 4);
     };
     lcap = lds_tile(c);
     lds_words = words(lcap);
@@ -1237,7 +1247,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     // tasks whose N+(u) exceeds the tile keep their sets in HBM
     for (int i = 0; i < nj; ++i)
       if (jobs[i].kind == kJobClique && jobs[i].cap > lcap)
-        need[i] = (int64_t)(std::max((int)jobs[i].k - 3, 0) + 1) * jobs[i].cap + 1;
+        need[i] = (int64_t)std::max((int)jobs[i].k - 3, 0) * jobs[i].cap + 1 + 2 * ((int64_t)jobs[i].cap + 1);
   }
 
   // local-graph tile: roots with more out-neighbours than the tile keep
@@ -1584,11 +1594,49 @@ static std::string query_key(const gpm_query& q) {
   return k;
 }
 
+// The checks a served query must pass before it gets a ticket: a known
+// graph, a valid kind and mode, a valid pattern, and a pattern the graph can
+// run (a DAG-only graph takes cliques only; motifs need the symmetric graph).
+static gpm_status check_query(gpm_ctx* c, const gpm_query& q) {
+  Graph* g = find_graph(c, q.graph_id);
+  if (!g) return fail(c, GPM_E_INVAL, "unknown graph id");
+  if (q.kind == GPM_QUERY_COUNT) {
+    if (q.mode_or_k != GPM_VERTEX_INDUCED && q.mode_or_k != GPM_EDGE_INDUCED)
+      return fail(c, GPM_E_INVAL, "bad induced mode");
+    std::string err;
+    gpm_status st = validate_pattern(q.pattern, &err);
+    if (st) return fail(c, st, err);
+    if (g->dag_only && !is_clique(q.pattern))
+      return fail(c, GPM_E_UNSUPPORTED, "non-clique pattern on a DAG-only graph");
+    return GPM_OK;
+  }
+  if (q.kind == GPM_QUERY_MOTIFS) {
+    if (q.mode_or_k != 3 && q.mode_or_k != 4) return fail(c, GPM_E_INVAL, "motif size must be 3 or 4");
+    if (g->dag_only) return fail(c, GPM_E_UNSUPPORTED, "motifs need the symmetric graph");
+    return GPM_OK;
+  }
+  return fail(c, GPM_E_INVAL, "bad query kind");
+}
+
+static void complete(gpm_ctx* c, int64_t ticket, gpm_status st, const std::string& err,
+                     const uint64_t* r) {
+  Done d;
+  d.st = st;
+  d.err = err;
+  if (r)
+    for (int i = 0; i < 6; ++i) d.r[i] = r[i];
+  c->done[ticket] = d;
+}
+
 // Collect finished launches, then admit pending queries into free slots.
 // Continuous batching with cost awareness: a query whose cost is unknown or
 // above serve_light_ms (measured when it last ran alone) gets a launch of
 // its own, so light queries never wait behind it; light queries are batched
-// together, up to max_batch per launch, in arrival order.
+// together, up to max_batch per launch, in arrival order.  Admission by
+// frontier memory (adaptive buffering, Sec. 7.2 (3)): a query whose buffers
+// do not fit what the running launches leave free waits, first in line,
+// until they finish; one that does not fit the whole budget completes with
+// GPM_E_NOMEM.  A query that cannot run completes with its error status.
 static gpm_status progress(gpm_ctx* c) {
   const int ns = n_serve_slots(c);
   for (int i = 1; i <= ns; ++i) {
@@ -1596,23 +1644,27 @@ static gpm_status progress(gpm_ctx* c) {
     if (!s.busy) continue;
     hipError_t e = hipEventQuery(s.ev1);
     if (e == hipErrorNotReady) continue;
-    if (e != hipSuccess) return fail(c, GPM_E_DEVICE, std::string("serving launch: ") + hipGetErrorString(e));
-    HIP_TRY(c, hipStreamSynchronize(s.stream));  // result copy queued after ev1
-    if (s.queries.size() == 1 && s.n_launch > 0) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, s.ev0, s.ev1) == hipSuccess) c->qcost[s.qkeys[0]] = ms;
-    }
-    for (auto& qw : s.queries) {
-      std::array<uint64_t, 6> r{};
-      finish_query(qw, s.h_res, r.data());
-      c->done[qw.ticket] = r;
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);  // result copy queued after ev1
+    if (e != hipSuccess) {
+      const std::string msg = std::string("serving launch: ") + hipGetErrorString(e);
+      for (auto& qw : s.queries) complete(c, qw.ticket, GPM_E_DEVICE, msg, nullptr);
+    } else {
+      if (s.queries.size() == 1 && s.n_launch > 0) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s.ev0, s.ev1) == hipSuccess) c->qcost[s.qkeys[0]] = ms;
+      }
+      for (auto& qw : s.queries) {
+        uint64_t r[6];
+        finish_query(qw, s.h_res, r);
+        complete(c, qw.ticket, GPM_OK, "", r);
+      }
+      s.zero_dirty = false;
+      s.tri_dirty = false;
     }
     s.queries.clear();
     s.qkeys.clear();
     s.busy = false;
     s.heavy = false;
-    s.zero_dirty = false;
-    s.tri_dirty = false;
     c->serve_frontier_in_use -= s.frontier_bytes_in_use;
     s.frontier_bytes_in_use = 0;
   }
@@ -1620,13 +1672,19 @@ static gpm_status progress(gpm_ctx* c) {
     auto it = c->qcost.find(query_key(q));
     return it != c->qcost.end() && it->second <= (double)c->opt_serve_light_ms;
   };
+  auto busy_slots = [&]() {
+    int b = 0;
+    for (int i = 1; i <= ns; ++i) b += c->slots[i].busy ? 1 : 0;
+    return b;
+  };
   // heavy (or not yet measured) queries run alone and may hold at most half
   // of the slots, so light queries keep slots of their own
   int heavy_busy = 0;
   for (int i = 1; i <= ns; ++i)
     if (c->slots[i].busy && c->slots[i].heavy) ++heavy_busy;
   const int heavy_max = std::max(1, ns / 2);
-  for (int i = 1; i <= ns && !c->pending.empty(); ++i) {
+  bool blocked = false;   // the head of the line waits for memory
+  for (int i = 1; i <= ns && !c->pending.empty() && !blocked; ++i) {
     Slot& s = c->slots[i];
     if (s.busy) continue;
     gpm_status st = slot_init(c, s, nullptr);
@@ -1634,6 +1692,7 @@ static gpm_status progress(gpm_ctx* c) {
     size_t avail = c->budget > c->serve_frontier_in_use ? c->budget - c->serve_frontier_in_use : 0;
     JobPlanSet js;
     std::vector<QueryWork> qs;
+    std::vector<Pending> taken;
     std::vector<std::string> keys;
     // the group starts at the first pending query this slot may take
     auto first = c->pending.begin();
@@ -1652,13 +1711,11 @@ static gpm_status progress(gpm_ctx* c) {
       size_t pbefore = js.plans.size();
       st = build_query(c, pq.q, js, qw);
       if (st) {
-        // a query that cannot run completes with an error marker (all ones)
+        // a query that cannot run completes with its status
         js.jobs.resize(before);
         js.need_words.resize(before);
         js.plans.resize(pbefore);
-        std::array<uint64_t, 6> r;
-        r.fill(~0ull);
-        c->done[pq.ticket] = r;
+        complete(c, pq.ticket, st, c->err, nullptr);
         it = c->pending.erase(it);
         continue;
       }
@@ -1667,14 +1724,24 @@ static gpm_status progress(gpm_ctx* c) {
       int64_t stride = 0;
       for (auto w : js.need_words) stride = std::max(stride, w);
       size_t min_bytes = (size_t)align_up((size_t)stride, 64) * 4 * (size_t)(c->cus);
-      if (!qs.empty() && min_bytes > avail) {
+      if (min_bytes > avail) {
         js.jobs.resize(before);
         js.need_words.resize(before);
         js.plans.resize(pbefore);
-        break;
+        if (!qs.empty()) break;   // the group is full; this query starts the next one
+        if (busy_slots() > 0) {
+          blocked = true;           // memory frees when a running launch finishes
+          break;
+        }
+        // nothing else holds memory: the query does not fit the whole budget
+        complete(c, pq.ticket, GPM_E_NOMEM,
+                 "the query's frontier buffers exceed the memory budget", nullptr);
+        it = c->pending.erase(it);
+        continue;
       }
       qw.ticket = pq.ticket;
       qs.push_back(qw);
+      taken.push_back(pq);
       keys.push_back(query_key(pq.q));
       it = c->pending.erase(it);
       if (!batchable) break;
@@ -1682,15 +1749,26 @@ static gpm_status progress(gpm_ctx* c) {
     if (qs.empty()) continue;
     if (js.jobs.empty()) {
       for (auto& qw : qs) {
-        std::array<uint64_t, 6> r{};
-        finish_query(qw, nullptr, r.data());
-        c->done[qw.ticket] = r;
+        uint64_t r[6];
+        finish_query(qw, nullptr, r);
+        complete(c, qw.ticket, GPM_OK, "", r);
       }
       continue;
     }
     size_t used = 0;
     st = launch_group(c, s, js, false, avail, &used);
-    if (st) return st;
+    if (st) {
+      if (st == GPM_E_NOMEM && busy_slots() > 0) {
+        // not enough memory beside the running launches: back to the head of
+        // the line, in arrival order, until one of them finishes
+        for (auto it = taken.rbegin(); it != taken.rend(); ++it) c->pending.push_front(*it);
+        blocked = true;
+      } else {
+        const std::string msg = c->err;
+        for (auto& qw : qs) complete(c, qw.ticket, st, msg, nullptr);
+      }
+      continue;
+    }
     s.queries = qs;
     s.qkeys = keys;
     s.busy = true;
@@ -1707,7 +1785,7 @@ static gpm_status progress(gpm_ctx* c) {
 // ---------------------------------------------------------------------------
 
 // Canonical-form checks of a CSR (Table 3's note: symmetric, no loops, no
-// duplicates; sorted lists, Sec. 3), plus symmetry / acyclicity with
+// duplicates; sorted lists, Sec. 4.2), plus symmetry / acyclicity with
 // GPM_VALIDATE.
 static gpm_status validate_csr(const HostCSR& h, uint32_t flags, std::string* why) {
   const int64_t n = h.n;
@@ -2264,27 +2342,31 @@ gpm_status gpm_submit(gpm_ctx* c, const gpm_query* q, int64_t* ticket_out) {
   if (!c || !q || !ticket_out) return GPM_E_INVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   if ((int64_t)c->pending.size() >= c->opt_max_pending) return fail(c, GPM_E_BUSY, "pending list full");
-  if (!find_graph(c, q->graph_id)) return fail(c, GPM_E_INVAL, "unknown graph id");
+  gpm_status st = check_query(c, *q);
+  if (st) return st;
   int64_t t = c->next_ticket++;
   c->pending.push_back(Pending{*q, t});
+  c->issued.insert(t);
   *ticket_out = t;
   return progress(c);
 }
 
 gpm_status gpm_poll(gpm_ctx* c, int64_t ticket, int* done_out, uint64_t* counts_out) {
   if (!c || !done_out) return GPM_E_INVAL;
+  *done_out = 0;
+  if (!c->issued.count(ticket)) return fail(c, GPM_E_INVAL, "unknown or already collected ticket");
   HIP_TRY(c, hipSetDevice(c->device));
   gpm_status st = progress(c);
   if (st) return st;
   auto it = c->done.find(ticket);
-  if (it == c->done.end()) {
-    *done_out = 0;
-    return GPM_OK;
-  }
-  if (counts_out)
-    for (int i = 0; i < 6; ++i) counts_out[i] = it->second[i];
+  if (it == c->done.end()) return GPM_OK;
+  Done d = std::move(it->second);
   c->done.erase(it);
+  c->issued.erase(ticket);
   *done_out = 1;
+  if (d.st != GPM_OK) return fail(c, d.st, d.err);
+  if (counts_out)
+    for (int i = 0; i < 6; ++i) counts_out[i] = d.r[i];
   return GPM_OK;
 }
 
@@ -2294,8 +2376,7 @@ gpm_status gpm_wait(gpm_ctx* c, int64_t ticket, int64_t timeout_ns, uint64_t* co
   for (;;) {
     int done = 0;
     gpm_status st = gpm_poll(c, ticket, &done, counts_out);
-    if (st) return st;
-    if (done) return GPM_OK;
+    if (st || done) return st;
     auto el = std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
     if (timeout_ns >= 0 && el >= timeout_ns) return fail(c, GPM_E_TIMEOUT, "wait timed out");
   }

@@ -6,7 +6,7 @@ produces, so it is deliberately kept free of any set operation, orientation,
 plan or count.
 
 Every generator returns a canonical undirected simple graph in CSR form
-(the input format of the graph loader, paper Sec. 3 "Graph Loader and
+(the input format of the graph loader, paper Sec. 4.2 "Graph Loader and
 Preprocessor" and Table 3's note that data graphs are symmetric with no loops
 or duplicate edges):
 

@@ -3,6 +3,8 @@
 Calls only the CPU oracle (oracle/) on graphs from the seeded generators;
 each record carries the sha256 of the generated CSR so a test can confirm
 it regenerated the same graph.  Run:  python tests/golden/gen_golden.py NAME
+(NAME: rmat_s20, rmat_s16, chung_lu_4m, batch256, or serve_pool with optional
+pattern list, largest scale and first degree-oriented scale).
 """
 import json
 import os
@@ -50,9 +52,70 @@ def batch_golden():
                    "seconds": round(time.time() - t0, 1), "graphs": recs}, f, indent=0)
 
 
-def main(name):
+# The patterns of the serving workload: (name, induced mode as served, route).
+# Cliques use the id-oriented DAG (the library orients by degree), edge-induced
+# 4-cycles the codegree count, diamond and tailed triangle the local triangle
+# terms.
+POOL_ROUTES = {
+    "triangle": lambda g, o: O.triangles(g, o),
+    "clique4": lambda g, o: O.cliques(g, 4, o),
+    "clique5": lambda g, o: O.cliques(g, 5, o),
+    "cycle4": lambda g, o: O.cycle4(g),
+    "diamond": lambda g, o: O.nonind4_local(g, o)[3],
+    "tailed_triangle": lambda g, o: O.nonind4_local(g, o)[2],
+}
+
+
+def pool_golden(patterns, max_scale, degree_from_scale):
+    """Oracle counts of the 32-graph serving pool (R-MAT ef 16, four graphs per
+    scale 16..23), one record per graph, written after every count so a long
+    run can be resumed; pairs already stored for the same CSR are skipped.
+    Cliques are counted on the id-oriented DAG below `degree_from_scale` and
+    on the (degree, id)-oriented one from that scale on (recorded per count).
+    """
+    path = os.path.join(HERE, "serve_pool_oracle.json")
+    db = {"workload": "serve_pool", "graphs": []}
+    if os.path.exists(path):
+        with open(path) as f:
+            db = json.load(f)
+    by_i = {r["i"]: r for r in db["graphs"]}
+    for i in range(32):
+        scale = 16 + i // 4
+        if scale > max_scale:
+            continue
+        todo = [p for p in patterns if p not in by_i.get(i, {}).get("counts", {})]
+        if not todo:
+            continue
+        g = synth.serve_pool_graph(i)
+        rec = by_i.get(i)
+        if rec is None or rec["sha256"] != g.sha256():
+            rec = {"i": i, "scale": scale, "n": g.n, "m": g.m, "max_degree": g.max_degree(),
+                   "sha256": g.sha256(), "counts": {}, "orientation": {}, "seconds": {},
+                   "oracle_threads": O.num_threads()}
+            by_i[i] = rec
+        for p in todo:
+            order = 1 if scale >= degree_from_scale else 0
+            t = time.time()
+            rec["counts"][p] = POOL_ROUTES[p](g, order)
+            rec["seconds"][p] = round(time.time() - t, 2)
+            if p in ("triangle", "clique4", "clique5", "diamond", "tailed_triangle"):
+                rec["orientation"][p] = "degree" if order else "id"
+            print(i, scale, p, rec["counts"][p], rec["seconds"][p], flush=True)
+            db["graphs"] = [by_i[j] for j in sorted(by_i)]
+            with open(path + ".tmp", "w") as f:
+                json.dump(db, f, indent=1)
+            os.replace(path + ".tmp", path)
+
+
+def main(name, *rest):
     if name == "batch256":
         return batch_golden()
+    if name == "serve_pool":
+        # serve_pool [patterns,comma,separated] [max_scale] [degree_from_scale]
+        pats = rest[0].split(",") if rest else list(POOL_ROUTES)
+        max_scale = int(rest[1]) if len(rest) > 1 else 23
+        deg_from = int(rest[2]) if len(rest) > 2 else 24
+        return pool_golden(pats, max_scale, deg_from)
     mk, items = WORKLOADS[name]
     g = mk()
     rec = {"workload": name, "generator": mk.__name__, "n": g.n, "m": g.m,
@@ -68,4 +131,4 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    main(*sys.argv[1:])

@@ -29,11 +29,11 @@ MUTATIONS = {
     "orient_ties_both_ways": ("return du < dv || (du == dv && u < v);",
                               "return du <= dv;"),
     "path4_triangle_term": ("np4 -= (u128)3 * T;", "np4 -= (u128)2 * T;"),
-    "tailed_degree_term": ("if (d >= 2) ntt += (u128)tv[u] * (d - 2);",
-                           "if (d >= 2) ntt += (u128)tv[u] * (d - 1);"),
-    "diamond_pairs": ("if (t >= 2) nd += t * (t - 1) / 2;", "if (t >= 2) nd += t * t / 2;"),
-    "star_binomial": ("if (d >= 3) ns3 += d * (d - 1) * (d - 2) / 6;",
-                      "if (d >= 3) ns3 += d * (d - 1) * (d - 2) / 2;"),
+    "tailed_degree_term": ("if (d >= 2) *ntt += (u128)tv[u] * (d - 2);",
+                           "if (d >= 2) *ntt += (u128)tv[u] * (d - 1);"),
+    "diamond_pairs": ("if (t >= 2) *nd += t * (t - 1) / 2;", "if (t >= 2) *nd += t * t / 2;"),
+    "star_binomial": ("if (d >= 3) *ns3 += d * (d - 1) * (d - 2) / 6;",
+                      "if (d >= 3) *ns3 += d * (d - 1) * (d - 2) / 2;"),
     "motif_k4_in_diamond": ("__int128 d = (__int128)N[4] - 6 * k4;",
                             "__int128 d = (__int128)N[4] - 5 * k4;"),
     "motif_cycle_in_diamond": ("__int128 c4 = (__int128)N[2] - d - 3 * k4;",
@@ -61,6 +61,10 @@ MUTATIONS = {
     "list_image_compare": ("if (t[s[i]] > t[i]) break;", "if (t[s[i]] > t[i]) continue;"),
     "list_row_columns": ("for (int d = 0; d < k; d++) t[pl->order[d]] = img[d];",
                          "for (int d = 0; d < k; d++) t[d] = img[d];"),
+    "trace_retrace_walks": ("u128 c4 = (tr4 + sd - 2 * sd2) / 8;", "u128 c4 = (tr4 + sd - sd2) / 8;"),
+    "trace_square": ("local += c * c;", "local += c * (c - 1);"),
+    "trace_diagonal_dropped": ("int64_t w = col[f];\n                    if (cnt[w]++ == 0)",
+                               "int64_t w = col[f];\n                    if (w == v) continue;\n                    if (cnt[w]++ == 0)"),
     "has_edge_search": ("if (col[mid] < v) lo = mid + 1; else hi = mid;\n    }\n    return lo < rp[u + 1]",
                         "if (col[mid] <= v) lo = mid + 1; else hi = mid;\n    }\n    return lo < rp[u + 1]"),
 }
@@ -97,6 +101,7 @@ def battery():
             check("Kmn motifs4", O.motifs4(g),
                   [0, a * C(b, 3) + b * C(a, 3), C(a, 2) * C(b, 2), 0, 0, 0])
             check("Kmn c4", O.cycle4(g), C(a, 2) * C(b, 2))
+            check("Kmn c4 trace", O.cycle4_trace(g), C(a, 2) * C(b, 2))
         parts = [3, 4, 5, 2, 6]
         g = synth.complete_multipartite(parts)
         for k in (3, 4, 5):
@@ -104,6 +109,8 @@ def battery():
             check("multipartite id", O.cliques(g, k, 0), exp)
             check("multipartite deg", O.cliques(g, k, 1), exp)
         check("grid", O.cycle4(synth.grid(5, 7)), 24)
+        check("grid trace", O.cycle4_trace(synth.grid(5, 7)), 24)
+        check("Kn c4 trace", O.cycle4_trace(synth.complete(8)), 3 * C(8, 4))
         check("path motifs", O.motifs4(synth.path(9)), [6, 0, 0, 0, 0, 0])
         check("star motifs", O.motifs4(synth.star(10)), [0, C(10, 3), 0, 0, 0, 0])
         check("cycle motifs", O.motifs4(synth.cycle(9)), [9, 0, 0, 0, 0, 0])
@@ -145,6 +152,7 @@ def battery():
         d = g.degrees().astype(float)
         c4 = (float(np.einsum("ij,ji->", A2, A2)) - 2 * (d * d).sum() + d.sum()) / 8
         check("trace4", O.cycle4(g), int(round(c4)))
+        check("trace4 sparse", O.cycle4_trace(g), int(round(c4)))
     except Exception as e:  # a mutant may also crash an assertion path
         fails.append(f"exception {e!r}")
     return fails

@@ -125,6 +125,8 @@ def test_paths_and_cycles(oracle, n):
     assert oracle.motifs3(p) == [n - 2, 0]
     c = synth.cycle(n)
     assert oracle.cycle4(c) == (1 if n == 4 else 0)
+    assert oracle.cycle4_trace(c) == (1 if n == 4 else 0)
+    assert oracle.cycle4_trace(p) == 0
     if n >= 5:
         assert oracle.motifs4(c) == [n, 0, 0, 0, 0, 0]
     assert oracle.motifs3(c) == ([n, 0] if n > 3 else [0, 1])
@@ -141,6 +143,7 @@ def test_star(oracle, leaves):
 def test_grid_cycles(oracle, r, c):
     g = synth.grid(r, c)
     assert oracle.cycle4(g) == (r - 1) * (c - 1)
+    assert oracle.cycle4_trace(g) == (r - 1) * (c - 1)
     assert oracle.triangles(g) == 0
     if r * c <= 30:
         assert oracle.count_embed(g, "cycle4", False) == (r - 1) * (c - 1)
@@ -150,6 +153,7 @@ def test_grid_cycles(oracle, r, c):
 def test_hypercube_cycles(oracle, d):
     g = synth.hypercube(d)
     assert oracle.cycle4(g) == C(d, 2) * 2 ** (d - 2)
+    assert oracle.cycle4_trace(g) == C(d, 2) * 2 ** (d - 2)
     assert oracle.count_embed(g, "cycle4", False) == C(d, 2) * 2 ** (d - 2)
 
 
@@ -185,6 +189,24 @@ def test_cycle4_trace(oracle):
         c4 = (tr4 - 2 * float((d * d).sum()) + float(d.sum())) / 8
         assert oracle.cycle4(g) == int(round(c4))
         assert oracle.count(g, "cycle4", False) == int(round(c4))
+        assert oracle.cycle4_trace(g) == int(round(c4))
+
+
+@pytest.mark.parametrize("n", [4, 5, 12, 40])
+def test_cycle4_trace_route_closed_forms(oracle, n):
+    """The closed-walk route (no ranking) on K_n, K_{m,n} and stars."""
+    assert oracle.cycle4_trace(synth.complete(n)) == 3 * C(n, 4)
+    assert oracle.cycle4_trace(synth.complete_bipartite(n, n + 3)) == C(n, 2) * C(n + 3, 2)
+    assert oracle.cycle4_trace(synth.star(n)) == 0
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_cycle4_routes_agree_power_law(oracle, seed):
+    """Codegree counting at the maximum-rank vertex and the closed-walk count
+    share neither code nor any ranking; hub-skewed graphs stress both."""
+    for g in [synth.rmat(13, 16, seed=seed),
+              synth.chung_lu(20000, 12.0, 2.1, 2000.0, 120000, seed)]:
+        assert oracle.cycle4(g) == oracle.cycle4_trace(g)
 
 
 # --- networkx ----------------------------------------------------------------
@@ -301,3 +323,21 @@ def test_overflow_detected(oracle):
     s = synth.star(5_000_000)
     with pytest.raises(oracle.OracleError):
         oracle.nonind4(s)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_nonind4_local_terms(oracle, seed):
+    """The local-term entry point returns the same path, star, tailed-triangle
+    and diamond counts as the full non-induced vector, and networkx's
+    monomorphism counts for the two triangle-based shapes."""
+    g = synth.erdos_renyi(40, 0.3, seed)
+    full = oracle.nonind4(g, 0)
+    assert oracle.nonind4_local(g, 0) == [full[0], full[1], full[3], full[4]]
+    assert oracle.nonind4_local(g, 1) == oracle.nonind4_local(g, 0)
+    G = to_nx(g)
+    for name, idx in (("tailed_triangle", 2), ("diamond", 3)):
+        P = nx.Graph(oracle.PATTERNS[name][1])
+        mono = sum(1 for _ in nx.algorithms.isomorphism.GraphMatcher(G, P)
+                   .subgraph_monomorphisms_iter()) // AUT[name]
+        assert oracle.nonind4_local(g, 0)[idx] == mono
+
