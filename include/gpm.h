@@ -387,6 +387,28 @@ gpm_status gpm_wait(gpm_ctx *ctx, int64_t ticket, int64_t timeout_ns,
 /* Number of queries submitted but not yet collected. */
 gpm_status gpm_inflight(gpm_ctx *ctx, int64_t *count_out);
 
+/* State of the serving loop (admission by frontier memory, Sec. 7.2 (3)),
+ * for monitoring and tests.  The call only reads: it does not progress the
+ * loop, so a launch that has finished on the device is counted as running
+ * until the next gpm_submit / gpm_poll / gpm_wait. */
+typedef struct {
+    int64_t pending;          /* accepted queries not yet admitted            */
+    int64_t running;          /* queries in launches on the device            */
+    int64_t completed;        /* completed queries whose result is not yet
+                                 collected                                    */
+    int64_t busy_slots;       /* launch slots with a launch in flight         */
+    int64_t frontier_in_use;  /* bytes of frontier and counter buffers the
+                                 running launches hold                        */
+    int64_t budget;           /* the context's memory budget (bytes)          */
+    int64_t memory_waits;     /* queries that had to wait, first in line, for
+                                 running launches to free memory (since
+                                 gpm_create)                                  */
+    int64_t admitted;         /* queries admitted into launches (since
+                                 gpm_create)                                  */
+} gpm_serve_info;
+
+gpm_status gpm_serve_state(gpm_ctx *ctx, gpm_serve_info *out);
+
 #ifdef __cplusplus
 }
 #endif

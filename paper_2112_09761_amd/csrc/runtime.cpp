@@ -138,6 +138,7 @@ struct Slot {
 struct Pending {
   gpm_query q;
   int64_t ticket;
+  bool waited = false;   // has waited for memory at the head of the line
 };
 
 // A completed served query: its status and, on GPM_OK, its results.
@@ -184,6 +185,8 @@ struct gpm_ctx {
   int64_t opt_serve_light_ms = 50;
   int64_t next_ticket = 1;
   size_t serve_frontier_in_use = 0;
+  int64_t serve_memory_waits = 0;   // queries that waited for memory at the head of the line
+  int64_t serve_admitted = 0;
   // listing: queue and match counters (device), their copy (pinned host)
   unsigned long long* d_list = nullptr;
   unsigned long long* h_list = nullptr;
@@ -1731,6 +1734,10 @@ static gpm_status progress(gpm_ctx* c) {
         if (!qs.empty()) break;   // the group is full; this query starts the next one
         if (busy_slots() > 0) {
           blocked = true;           // memory frees when a running launch finishes
+          if (!it->waited) {
+            it->waited = true;
+            ++c->serve_memory_waits;
+          }
           break;
         }
         // nothing else holds memory: the query does not fit the whole budget
@@ -1761,6 +1768,10 @@ static gpm_status progress(gpm_ctx* c) {
       if (st == GPM_E_NOMEM && busy_slots() > 0) {
         // not enough memory beside the running launches: back to the head of
         // the line, in arrival order, until one of them finishes
+        if (!taken[0].waited) {
+          taken[0].waited = true;
+          ++c->serve_memory_waits;
+        }
         for (auto it = taken.rbegin(); it != taken.rend(); ++it) c->pending.push_front(*it);
         blocked = true;
       } else {
@@ -1772,6 +1783,7 @@ static gpm_status progress(gpm_ctx* c) {
     s.queries = qs;
     s.qkeys = keys;
     s.busy = true;
+    c->serve_admitted += (int64_t)qs.size();
     s.heavy = !batchable;
     if (s.heavy) ++heavy_busy;
     s.frontier_bytes_in_use = used;
@@ -2380,6 +2392,23 @@ gpm_status gpm_wait(gpm_ctx* c, int64_t ticket, int64_t timeout_ns, uint64_t* co
     auto el = std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
     if (timeout_ns >= 0 && el >= timeout_ns) return fail(c, GPM_E_TIMEOUT, "wait timed out");
   }
+}
+
+gpm_status gpm_serve_state(gpm_ctx* c, gpm_serve_info* out) {
+  if (!c || !out) return GPM_E_INVAL;
+  gpm_serve_info r{};
+  r.pending = (int64_t)c->pending.size();
+  r.completed = (int64_t)c->done.size();
+  for (int i = 1; i <= kMaxSlots; ++i) {
+    r.running += (int64_t)c->slots[i].queries.size();
+    r.busy_slots += c->slots[i].busy ? 1 : 0;
+  }
+  r.frontier_in_use = (int64_t)c->serve_frontier_in_use;
+  r.budget = (int64_t)c->budget;
+  r.memory_waits = c->serve_memory_waits;
+  r.admitted = c->serve_admitted;
+  *out = r;
+  return GPM_OK;
 }
 
 gpm_status gpm_inflight(gpm_ctx* c, int64_t* count_out) {

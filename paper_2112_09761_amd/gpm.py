@@ -40,7 +40,7 @@ EXPORTS = [
     "gpm_load_csr", "gpm_unload", "gpm_graph_info", "gpm_pattern_clique",
     "gpm_pattern_named", "gpm_pattern_from_edges", "gpm_plan", "gpm_frontier_waves",
     "gpm_count", "gpm_motifs", "gpm_count_batch", "gpm_submit", "gpm_poll", "gpm_wait",
-    "gpm_inflight", "gpm_validate_csr", "gpm_prepare", "gpm_list",
+    "gpm_inflight", "gpm_validate_csr", "gpm_prepare", "gpm_list", "gpm_serve_state",
 ]
 
 
@@ -93,6 +93,13 @@ class Stats(ctypes.Structure):
         return d
 
 
+class ServeInfo(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("busy_slots", ctypes.c_int64),
+                ("frontier_in_use", ctypes.c_int64), ("budget", ctypes.c_int64),
+                ("memory_waits", ctypes.c_int64), ("admitted", ctypes.c_int64)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("clique", ctypes.c_int32), ("aut", ctypes.c_int32),
                 ("root_bound", ctypes.c_int32), ("n_buffers", ctypes.c_int32),
@@ -141,6 +148,7 @@ def lib():
         L.gpm_poll.argtypes = [c_vp, c_i64, P(ctypes.c_int), P(c_u64)]
         L.gpm_wait.argtypes = [c_vp, c_i64, c_i64, P(c_u64)]
         L.gpm_inflight.argtypes = [c_vp, P(c_i64)]
+        L.gpm_serve_state.argtypes = [c_vp, P(ServeInfo)]
         L.gpm_validate_csr.argtypes = [c_i64, c_i64, c_vp, c_vp, ctypes.c_uint32]
         L.gpm_prepare.argtypes = [c_vp, c_i32]
         for name in EXPORTS:
@@ -381,6 +389,11 @@ class Context:
         out = (c_u64 * 6)()
         self._ck(lib().gpm_wait(self._h, ticket, timeout_ns, out))
         return [int(x) for x in out]
+
+    def serve_state(self) -> dict:
+        r = ServeInfo()
+        self._ck(lib().gpm_serve_state(self._h, ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in r._fields_}
 
     def inflight(self) -> int:
         n = c_i64()

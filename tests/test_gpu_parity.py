@@ -478,6 +478,71 @@ def test_serving_counter_buffers_grow(ctx, oracle):
             ctx.unload(gid)
 
 
+def test_serving_admission_waits_for_memory(oracle):
+    """Admission by frontier memory (adaptive buffering, Sec. 7.2 (3)): with a
+    budget that one running query fills, a second query that does not fit
+    beside it waits, first in line, and completes after it with the oracle's
+    count; a query whose buffers exceed the whole budget completes with
+    GPM_E_NOMEM through gpm_wait; an unknown ticket is refused at once."""
+    import time
+    import torch
+    from paper_2112_09761_amd import gpm
+    g = synth.rmat(16, 16, seed=1601)
+    small = synth.rmat(10, 8, seed=1602)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    with gpm.Context(0, torch.cuda.current_stream()) as c0:
+        gid = c0.load(g)
+        dmax = c0.graph_info(gid)["max_degree"]
+    x = gpm.plan("diamond", E)["n_buffers"]
+    assert x >= 1
+    stride = -(-x * dmax // 64) * 64            # frontier words per wave
+    min_bytes = stride * 4 * cus                # one wave per CU
+    exp_big = oracle.count(g, "diamond", False)
+    exp_small = oracle.count(small, "diamond", False)
+    with gpm.Context(0, torch.cuda.current_stream(), budget=min_bytes * 3 // 2) as c:
+        c.set_option("decompose", 0)            # the DFS plan: it needs frontier memory
+        ids = [c.load(g), c.load(small)]
+        t_alone = time.perf_counter()
+        assert c.count(ids[0], "diamond", E) == exp_big
+        t_alone = time.perf_counter() - t_alone
+        st0 = c.serve_state()
+        t1 = c.submit(gpm.count_query(ids[0], "diamond", E))
+        t2 = c.submit(gpm.count_query(ids[1], "diamond", E))
+        st = c.serve_state()
+        # the first launch holds more than half the budget, so the second
+        # query cannot start beside it
+        assert st["running"] == 1 and st["pending"] == 1, (st, t_alone)
+        assert st["frontier_in_use"] > st["budget"] - min_bytes, st
+        assert st["memory_waits"] == st0["memory_waits"] + 1, st
+        done2, _ = c.poll(t2)
+        assert not done2 or c.serve_state()["running"] == 0
+        assert c.wait(t1)[0] == exp_big
+        assert c.wait(t2)[0] == exp_small
+        st = c.serve_state()
+        assert st["pending"] == 0 and st["running"] == 0 and st["frontier_in_use"] == 0, st
+        assert st["admitted"] == st0["admitted"] + 2, st
+        with pytest.raises(gpm.GpmError) as e:
+            c.wait(987654321)
+        assert e.value.status == -1
+        with pytest.raises(gpm.GpmError) as e:
+            c.wait(t1)                          # already collected
+        assert e.value.status == -1
+        # a budget below one wave per CU: the query completes with NOMEM
+        c.set_option("budget", min_bytes // 4)
+        t3 = c.submit(gpm.count_query(ids[0], "diamond", E))
+        with pytest.raises(gpm.GpmError) as e:
+            c.wait(t3)
+        assert e.value.status == -4
+        assert c.inflight() == 0
+        # submit-time checks: no ticket for a query that cannot run
+        with pytest.raises(gpm.GpmError) as e:
+            c.submit(gpm.count_query(ids[0], (4, [(0, 1), (2, 3)]), E))
+        assert e.value.status == -3
+        with pytest.raises(gpm.GpmError) as e:
+            c.submit(gpm.count_query(12345, "triangle", E))
+        assert e.value.status == -1
+
+
 def test_edge_terms_fallback_with_large_roots(ctx, oracle):
     """Per-edge motif terms: with roots beyond the local-graph limit the
     triangle scatter cannot see every triangle, so the per-edge intersections
@@ -501,10 +566,19 @@ def test_edge_terms_fallback_with_large_roots(ctx, oracle):
             ctx.unload(gid)
 
 
-def test_error_paths_on_device(ctx, oracle):
+def test_error_paths_on_device(oracle):
     """Load-time validation, unknown ids, bad modes, unsupported patterns on a
     DAG-only graph, a memory budget too small for any frontier, and a full
-    serving queue all return their status codes (no abort, no count)."""
+    serving queue all return their status codes (no abort, no count).  The
+    test changes the budget, so it runs on a context of its own."""
+    import numpy as np
+    import torch
+    from paper_2112_09761_amd import gpm
+    with gpm.Context(0, torch.cuda.current_stream()) as ctx:
+        _error_paths(ctx, oracle)
+
+
+def _error_paths(ctx, oracle):
     import numpy as np
     from paper_2112_09761_amd import gpm
     with pytest.raises(gpm.GpmError) as e:

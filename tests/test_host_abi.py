@@ -37,7 +37,7 @@ def test_struct_layouts_match_c_compiler(tmp_path):
     import subprocess
     structs = {"gpm_stats": gpm.Stats, "gpm_graph_meta": gpm.GraphMeta,
                "gpm_plan_info": gpm.PlanInfo, "gpm_pattern": gpm.Pattern,
-               "gpm_query": gpm.Query}
+               "gpm_query": gpm.Query, "gpm_serve_info": gpm.ServeInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gpm.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
