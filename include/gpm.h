@@ -291,6 +291,31 @@ gpm_status gpm_frontier_waves(int64_t free_bytes, int32_t x_levels,
 gpm_status gpm_count(gpm_ctx *ctx, int32_t graph_id, const gpm_pattern *pattern,
                      int mode, uint64_t *count_out);
 
+/* gpm_count without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, semantics and errors as gpm_count; the
+ * call allocates no device or pinned host memory (no hipMalloc, hipFree or
+ * hipHostMalloc): the job table, queue counters, result slots and frontier /
+ * counter buffers of the call live in a device scratch array of 64 MiB that
+ * the library holds per GPU until the process ends (its address is looked up
+ * once per device at gpm_create), and the host staging was reserved at
+ * gpm_create.  Requirements and limits:
+ *   - the graph must already hold what the query needs (orientation,
+ *     relabelling, root lists): run gpm_count with the same pattern and mode
+ *     once first (or gpm_prepare where it covers it); else GPM_E_UNSUPPORTED
+ *     and nothing is built;
+ *   - frontier sizing works within the scratch (fewer waves when buffers are
+ *     large); a query whose buffers for one workgroup's waves, or whose job
+ *     tables, exceed it fails with GPM_E_NOMEM;
+ *   - every call on a GPU uses that GPU's one scratch array: calls that
+ *     overlap on one GPU (two contexts of the device, or several host
+ *     threads) race and give wrong counts.  Sequential calls are safe: the
+ *     call returns after its results are on the host, and it clears every
+ *     buffer that must start at zero. */
+gpm_status gpm_count_noalloc(gpm_ctx *ctx, int32_t graph_id,
+                             const gpm_pattern *pattern, int mode,
+                             uint64_t *count_out);
+
 /* Vertex-induced counts of every connected k-vertex pattern (k-motif
  * counting, Sec. 2.1), k = 3 or 4, written to counts_out[len]:
  *   k = 3 (len >= 2): [wedge, triangle]

@@ -13,6 +13,8 @@ constexpr int kWavesPerBlock = 4;       // 256-thread workgroups of four wave64s
 constexpr int kQueues = 8;              // one task queue per XCD
 constexpr int kQueueStride = 16;        // uint64 words between queue counters (128 B)
 constexpr int kResultFields = 8;        // uint64 counters per result slot
+// Device scratch of the allocation-free count, per GPU (see scratch_address)
+constexpr size_t kScratchBytes = size_t(64) << 20;
 
 // One depth of a search plan (Sec. 2.2: the matching order fixes which
 // earlier pattern vertices a new vertex must be adjacent to -- its candidate
@@ -182,5 +184,9 @@ int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max
                      size_t lds_bytes, void* stream);
 int launch_list(const ListArgs& a, int blocks, void* stream);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
+
+// Device address of this GPU's copy of the allocation-free count's scratch
+// (kScratchBytes); `device` must be the current device.  Returns a hipError_t.
+int scratch_address(int device, void** ptr);
 
 }  // namespace gpm

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "gpm_internal.h"
 
@@ -1934,6 +1935,35 @@ int launch_list(const ListArgs& a, int blocks, void* stream) {
   hipLaunchKernelGGL(gpm_list, dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), 0,
                      (hipStream_t)stream, a);
   return (int)hipGetLastError();
+}
+
+// Device scratch of the allocation-free count (gpm_count_noalloc): job
+// table, queue counters, result slots, frontier and counter buffers of one
+// synchronous call.  One copy per GPU, loaded with the code object and held
+// until the process ends; calls that overlap on one GPU share it.  Host code
+// never uses the array's name (a host-side stand-in): its device address
+// comes from hipGetSymbolAddress, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+int scratch_address(int device, void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices || !ptr) return (int)hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return (int)e;
+    if (cur != device) return (int)hipErrorInvalidDevice;  // the caller makes it current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return 0;
 }
 
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream) {

@@ -124,6 +124,7 @@ struct Slot {
   bool tri_dirty = true;
   void* h_stage = nullptr; size_t h_stage_bytes = 0;    // pinned
   unsigned long long* h_res = nullptr; size_t h_res_words = 0;  // pinned
+  const unsigned long long* h_out = nullptr;  // where the last group's results land
   bool busy = false;
   bool heavy = false;      // serving: the running group is a heavy or unknown query
   size_t frontier_bytes_in_use = 0;
@@ -149,6 +150,11 @@ struct Done {
 };
 
 }  // namespace
+
+// Host staging of the allocation-free count, reserved at gpm_create: the job
+// table of one query and its result words.
+constexpr size_t kNoallocStageBytes = 256 * 1024;
+constexpr size_t kNoallocResultWords = 8192;
 
 struct gpm_ctx {
   int device = 0;
@@ -187,6 +193,13 @@ struct gpm_ctx {
   size_t serve_frontier_in_use = 0;
   int64_t serve_memory_waits = 0;   // queries that waited for memory at the head of the line
   int64_t serve_admitted = 0;
+  // allocation-free count: this device's scratch (device address), host
+  // staging reserved at creation, and the flag that makes every path that
+  // would allocate (graph preparation, buffer growth) fail instead
+  void* scratch = nullptr;
+  bool noalloc = false;
+  std::vector<char> na_stage;
+  std::vector<unsigned long long> na_res;
   // listing: queue and match counters (device), their copy (pinned host)
   unsigned long long* d_list = nullptr;
   unsigned long long* h_list = nullptr;
@@ -208,8 +221,17 @@ static gpm_status fail(gpm_ctx* c, gpm_status st, const std::string& msg) {
       return fail((c), GPM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+// The allocation-free count found a structure of the graph missing (it
+// would have to build it, which allocates).
+static gpm_status not_prepared(gpm_ctx* c) {
+  return fail(c, GPM_E_UNSUPPORTED,
+              "the allocation-free count needs the graph prepared for this query "
+              "(run gpm_count with the same pattern and mode once first)");
+}
+
 template <typename T>
 static gpm_status dev_upload(gpm_ctx* c, T** dst, const T* src, size_t count) {
+  if (c->noalloc) return not_prepared(c);
   *dst = nullptr;
   if (count == 0) count = 1;
   HIP_TRY(c, hipMalloc((void**)dst, count * sizeof(T)));
@@ -288,6 +310,7 @@ static gpm_status ensure_ren(gpm_ctx* c, Graph& g);
 // orientation halves the edges and shrinks the maximum degree).
 static gpm_status ensure_dag(gpm_ctx* c, Graph& g) {
   if (g.dag_ready) return GPM_OK;
+  if (c->noalloc) return not_prepared(c);
   if (g.dag_only) {
     g.dag_host = g.host;
   } else {
@@ -322,6 +345,7 @@ static gpm_status ensure_dag(gpm_ctx* c, Graph& g) {
 // long tasks start early; plus the DAG edges of vertices too large for it.
 static gpm_status ensure_lgs(gpm_ctx* c, Graph& g, int64_t lgs_max) {
   if (g.lgs_ready && g.lgs_max_used == lgs_max) return GPM_OK;
+  if (c->noalloc) return not_prepared(c);
   if (g.lgs_ready) {
     dev_free(g.lgs_vtx);
     dev_free(g.big_src);
@@ -383,6 +407,7 @@ static gpm_status ensure_lgs(gpm_ctx* c, Graph& g, int64_t lgs_max) {
 // Root edges (v0, v1) with v1 < v0: one direction per undirected edge.
 static gpm_status ensure_lower(gpm_ctx* c, Graph& g) {
   if (g.lo_ready) return GPM_OK;
+  if (c->noalloc) return not_prepared(c);
   std::vector<int32_t> s, d;
   s.reserve(g.m);
   d.reserve(g.m);
@@ -410,6 +435,7 @@ static gpm_status ensure_lgs_split(gpm_ctx* c, Graph& g, int which, int k, int64
   Graph::SplitTasks& T = g.lgs_split[which][k];
   const int64_t key = (lo << 40) ^ (hi << 8) ^ waves ^ (g.lgs_max_used << 50);
   if (T.key == key) { *out = &T; return GPM_OK; }
+  if (c->noalloc) return not_prepared(c);
   dev_free(T.src);
   dev_free(T.dst);
   T = Graph::SplitTasks{};
@@ -467,6 +493,7 @@ static gpm_status lower_edges(gpm_ctx* c, const HostCSR& h, int32_t** src, int32
 // and rename vertices by degree).  Counts are invariant under relabelling.
 static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
   if (g.ren_ready) return GPM_OK;
+  if (c->noalloc) return not_prepared(c);
   const HostCSR& h = g.host;
   std::vector<int32_t> order(h.n), rank(h.n);
   for (int64_t u = 0; u < h.n; ++u) order[u] = (int32_t)u;
@@ -507,6 +534,7 @@ static gpm_status ensure_wedge(gpm_ctx* c, Graph& g, int64_t waves) {
   gpm_status st = ensure_ren(c, g);
   if (st) return st;
   if (g.wedge_key == waves) return GPM_OK;
+  if (c->noalloc) return not_prepared(c);
   dev_free(g.wedge_src);
   dev_free(g.wedge_dst);
   g.wedge_src = g.wedge_dst = nullptr;
@@ -1141,6 +1169,7 @@ static void slot_free(Slot& s) {
 
 static gpm_status grow_dev(gpm_ctx* c, void** p, size_t* have, size_t need) {
   if (*have >= need) return GPM_OK;
+  if (c->noalloc) return fail(c, GPM_E_DEVICE, "buffer growth in the allocation-free count");
   dev_free(*p);
   *p = nullptr;
   *have = 0;
@@ -1152,6 +1181,7 @@ static gpm_status grow_dev(gpm_ctx* c, void** p, size_t* have, size_t need) {
 
 static gpm_status grow_host(gpm_ctx* c, void** p, size_t* have, size_t need) {
   if (*have >= need) return GPM_OK;
+  if (c->noalloc) return fail(c, GPM_E_DEVICE, "buffer growth in the allocation-free count");
   if (*p) (void)hipHostFree(*p);
   *p = nullptr;
   *have = 0;
@@ -1211,10 +1241,21 @@ static std::vector<LaunchPlan> plan_launches(JobPlanSet& js, std::vector<int>& p
   return out;
 }
 
+// Device memory of one synchronous group that the library must not allocate:
+// every buffer of the group is carved from it.
+struct Arena {
+  char* base;
+  size_t bytes;
+};
+
 // Size, stage and enqueue the launches of one group on slot s.  Results land
-// in s.h_res (pinned) when s.ev1 completes.
+// in s.h_out when s.ev1 completes: the slot's pinned buffer, or with an arena
+// the context's reserved host buffer (device buffers then come from the arena,
+// nothing is allocated, and the zero-initialised counters are cleared on
+// every call, since the arena keeps what the last call left).
 static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission,
-                               size_t frontier_budget, size_t* frontier_used) {
+                               size_t frontier_budget, size_t* frontier_used,
+                               const Arena* ar = nullptr) {
   gpm_status st = slot_init(c, s, s.stream);
   if (st) return st;
   std::vector<int> perm;
@@ -1226,6 +1267,36 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     jobs[i] = js.jobs[perm[i]];
     need[i] = js.need_words[perm[i]];
     jobs[i].slot = perm[i];  // result slot = the job's original index
+  }
+
+  // staging layout: jobs | plans | per launch (jbeg, qbeg); device result
+  // words: results [nj * 8] | queues [launches * 8 * 16] | counters [launches * 4]
+  size_t off_jobs = 0;
+  size_t off_plans = align_up(off_jobs + sizeof(Job) * nj, 256);
+  size_t off_l = align_up(off_plans + sizeof(Plan) * std::max<size_t>(js.plans.size(), 1), 256);
+  std::vector<size_t> off_jbeg(launches.size()), off_qbeg(launches.size());
+  {
+    size_t cur = off_l;
+    for (size_t i = 0; i < launches.size(); ++i) {
+      off_jbeg[i] = cur;
+      cur = align_up(cur + 8 * ((size_t)launches[i].count + 1), 64);
+      off_qbeg[i] = cur;
+      cur = align_up(cur + 8 * (kQueues + 1), 64);
+    }
+    off_l = cur;
+  }
+  const size_t meta_bytes = off_l;
+  const size_t res_words = (size_t)nj * kResultFields;
+  const size_t q_words = launches.size() * kQueues * kQueueStride;
+  const size_t all_words = res_words + q_words + 4 * std::max<size_t>(launches.size(), 1);
+  // with an arena: meta | results, then the frontier and counter buffers
+  size_t arena_fixed = 0;
+  if (ar) {
+    arena_fixed = align_up(meta_bytes, 256) + align_up(all_words * 8, 256);
+    if (meta_bytes > c->na_stage.size() || all_words > c->na_res.size() ||
+        arena_fixed > ar->bytes)
+      return fail(c, GPM_E_NOMEM, "the query's job tables exceed the allocation-free scratch");
+    frontier_budget = ar->bytes - arena_fixed;
   }
 
   // LDS tile of the clique kernel: U | F_2 .. F_{k-2} | pad | P (int64) per wave
@@ -1313,12 +1384,25 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   waves = std::max<int64_t>(kWavesPerBlock, waves / kWavesPerBlock * kWavesPerBlock);
   const int blocks = (int)(waves / kWavesPerBlock);
   const size_t fbytes = (size_t)waves * (size_t)stride * 4;
+  int32_t* fbuf = nullptr;
   if (fbytes) {
-    st = grow_dev(c, (void**)&s.d_fbuf, &s.d_fbuf_bytes, fbytes);
-    if (st) return st;
+    if (ar) {
+      fbuf = (int32_t*)(ar->base + arena_fixed);
+    } else {
+      st = grow_dev(c, (void**)&s.d_fbuf, &s.d_fbuf_bytes, fbytes);
+      if (st) return st;
+      fbuf = s.d_fbuf;
+    }
   }
   const size_t zbytes = (size_t)waves * (size_t)zstride * 4;
-  if (zbytes) {
+  unsigned int* zbuf = nullptr;
+  if (zbytes && ar) {
+    if (fbytes + zbytes > frontier_budget)
+      return fail(c, GPM_E_NOMEM, "wedge counters exceed the allocation-free scratch");
+    zbuf = (unsigned int*)(ar->base + arena_fixed + fbytes);
+    if (launch_fill_u64((unsigned long long*)zbuf, (int64_t)(zbytes / 8), 0ull, s.stream))
+      return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+  } else if (zbytes) {
     // a reallocation may return the same address with new, uncleared memory
     // beyond the old size: any change of capacity needs the fill
     const size_t cap_before = s.d_zero_bytes;
@@ -1331,6 +1415,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
         return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
     }
     s.zero_dirty = true;  // until this group completes (every task restores zeros)
+    zbuf = s.d_zero;
   }
   // per-edge triangle counters: one region per scatter group (its DAG edge
   // count, from the group's edge-term job), zero between launches
@@ -1345,21 +1430,29 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   if (tbytes) {
     if (fbytes + zbytes + tbytes > frontier_budget)
       return fail(c, GPM_E_NOMEM, "per-edge triangle counters do not fit the memory budget");
-    const size_t cap_before = s.d_tri_bytes;  // (as for the wedge counters above)
-    st = grow_dev(c, (void**)&s.d_tri, &s.d_tri_bytes, tbytes);
-    if (st) return st;
-    if (s.d_tri_bytes != cap_before) s.tri_dirty = true;
-    if (s.tri_dirty) {
-      if (launch_fill_u64((unsigned long long*)s.d_tri, (int64_t)(s.d_tri_bytes / 8), 0ull,
-                          s.stream))
+    unsigned int* tri = nullptr;
+    if (ar) {
+      tri = (unsigned int*)(ar->base + arena_fixed + fbytes + zbytes);
+      if (launch_fill_u64((unsigned long long*)tri, (int64_t)(tbytes / 8), 0ull, s.stream))
         return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+    } else {
+      const size_t cap_before = s.d_tri_bytes;  // (as for the wedge counters above)
+      st = grow_dev(c, (void**)&s.d_tri, &s.d_tri_bytes, tbytes);
+      if (st) return st;
+      if (s.d_tri_bytes != cap_before) s.tri_dirty = true;
+      if (s.tri_dirty) {
+        if (launch_fill_u64((unsigned long long*)s.d_tri, (int64_t)(s.d_tri_bytes / 8), 0ull,
+                            s.stream))
+          return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+      }
+      s.tri_dirty = true;  // until this group completes (the edge-term jobs restore zeros)
+      tri = s.d_tri;
     }
-    s.tri_dirty = true;  // until this group completes (the edge-term jobs restore zeros)
     for (int i = 0; i < nj; ++i)
       if (jobs[i].tri_group > 0) {
         auto it = tri_off.find(jobs[i].tri_group);
         if (it == tri_off.end()) return fail(c, GPM_E_DEVICE, "triangle scatter without edge terms");
-        jobs[i].tri = s.d_tri + it->second;
+        jobs[i].tri = tri + it->second;
       }
   }
   *frontier_used = fbytes + zbytes + tbytes;
@@ -1379,36 +1472,21 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     L.blocks = blocks;
   }
 
-  // staging: jobs | plans | per launch (jbeg, qbeg)
-  size_t off_jobs = 0;
-  size_t off_plans = align_up(off_jobs + sizeof(Job) * nj, 256);
-  size_t off_l = align_up(off_plans + sizeof(Plan) * std::max<size_t>(js.plans.size(), 1), 256);
-  std::vector<size_t> off_jbeg(launches.size()), off_qbeg(launches.size());
-  size_t cur = off_l;
-  for (size_t i = 0; i < launches.size(); ++i) {
-    off_jbeg[i] = cur;
-    cur = align_up(cur + 8 * launches[i].jbeg.size(), 64);
-    off_qbeg[i] = cur;
-    cur = align_up(cur + 8 * (kQueues + 1), 64);
-  }
-  const size_t meta_bytes = cur;
-  st = grow_host(c, &s.h_stage, &s.h_stage_bytes, meta_bytes);
-  if (st) return st;
-  st = grow_dev(c, &s.d_meta, &s.d_meta_bytes, meta_bytes);
-  if (st) return st;
-  char* h = (char*)s.h_stage;
-  std::memcpy(h + off_jobs, jobs.data(), sizeof(Job) * nj);
-  if (!js.plans.empty()) std::memcpy(h + off_plans, js.plans.data(), sizeof(Plan) * js.plans.size());
-  for (size_t i = 0; i < launches.size(); ++i) {
-    std::memcpy(h + off_jbeg[i], launches[i].jbeg.data(), 8 * launches[i].jbeg.size());
-    std::memcpy(h + off_qbeg[i], launches[i].qbeg, 8 * (kQueues + 1));
-  }
-  // device result words: results [nj * 8] | queues [launches * 8 * 16] |
-  // counters [launches * 4]
-  const size_t res_words = (size_t)nj * kResultFields;
-  const size_t q_words = launches.size() * kQueues * kQueueStride;
-  const size_t all_words = res_words + q_words + 4 * std::max<size_t>(launches.size(), 1);
-  {
+  // staging
+  char* h = nullptr;
+  char* dm = nullptr;
+  unsigned long long* dres = nullptr;
+  unsigned long long* hres = nullptr;
+  if (ar) {
+    h = c->na_stage.data();
+    dm = ar->base;
+    dres = (unsigned long long*)(ar->base + align_up(meta_bytes, 256));
+    hres = c->na_res.data();
+  } else {
+    st = grow_host(c, &s.h_stage, &s.h_stage_bytes, meta_bytes);
+    if (st) return st;
+    st = grow_dev(c, &s.d_meta, &s.d_meta_bytes, meta_bytes);
+    if (st) return st;
     size_t have = s.d_res_words * 8;
     st = grow_dev(c, (void**)&s.d_res, &have, all_words * 8);
     if (st) return st;
@@ -1417,10 +1495,19 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     st = grow_host(c, (void**)&s.h_res, &hh, all_words * 8);
     if (st) return st;
     s.h_res_words = hh / 8;
+    h = (char*)s.h_stage;
+    dm = (char*)s.d_meta;
+    dres = s.d_res;
+    hres = s.h_res;
   }
-  char* dm = (char*)s.d_meta;
+  std::memcpy(h + off_jobs, jobs.data(), sizeof(Job) * nj);
+  if (!js.plans.empty()) std::memcpy(h + off_plans, js.plans.data(), sizeof(Plan) * js.plans.size());
+  for (size_t i = 0; i < launches.size(); ++i) {
+    std::memcpy(h + off_jbeg[i], launches[i].jbeg.data(), 8 * launches[i].jbeg.size());
+    std::memcpy(h + off_qbeg[i], launches[i].qbeg, 8 * (kQueues + 1));
+  }
   HIP_TRY(c, hipMemcpyAsync(dm, h, meta_bytes, hipMemcpyHostToDevice, s.stream));
-  if (launch_fill_u64(s.d_res, (int64_t)all_words, 0ull, s.stream))
+  if (launch_fill_u64(dres, (int64_t)all_words, 0ull, s.stream))
     return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
   HIP_TRY(c, hipEventRecord(s.ev0, s.stream));
   int n_launch = 0;
@@ -1434,15 +1521,15 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     a.lds_cap = lcap;
     a.plans = (const Plan*)(dm + off_plans);
     a.queue_begin = (const int64_t*)(dm + off_qbeg[i]);
-    a.queue_cnt = s.d_res + res_words + i * kQueues * kQueueStride;
-    a.results = s.d_res;
-    a.counters = s.d_res + res_words + q_words + 4 * i;
-    a.fbuf = fbytes ? s.d_fbuf : nullptr;
+    a.queue_cnt = dres + res_words + i * kQueues * kQueueStride;
+    a.results = dres;
+    a.counters = dres + res_words + q_words + 4 * i;
+    a.fbuf = fbuf;
     a.wave_stride = stride;
     const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs | kKindTriScatter)) != 0;
     a.lds_words = uses_lds ? lds_words : 0;
     a.lgs_tile = lgs_T;
-    a.zbuf = (L.kinds & kKindCycleWedge) ? s.d_zero : nullptr;
+    a.zbuf = (L.kinds & kKindCycleWedge) ? zbuf : nullptr;
     a.zstride = zstride;
     a.zlist = (int32_t)zlist;
     size_t lb = uses_lds ? lds_bytes : 0;
@@ -1462,7 +1549,8 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     ++n_launch;
   }
   HIP_TRY(c, hipEventRecord(s.ev1, s.stream));
-  HIP_TRY(c, hipMemcpyAsync(s.h_res, s.d_res, all_words * 8, hipMemcpyDeviceToHost, s.stream));
+  HIP_TRY(c, hipMemcpyAsync(hres, dres, all_words * 8, hipMemcpyDeviceToHost, s.stream));
+  s.h_out = hres;
   s.n_jobs = nj;
   s.n_launch = n_launch;
   s.n_lstats = std::min(n_launch, GPM_MAX_LAUNCH_STATS);
@@ -1491,7 +1579,7 @@ static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
     HIP_TRY(c, hipEventElapsedTime(&lm, i ? s.evl[i - 1] : s.ev0, s.evl[i]));
     c->stats.launch_ms[i] = lm;
     c->stats.launch_kinds[i] = s.lkinds[i];
-    const unsigned long long* ct = s.h_res + s.counters_off + 4 * (size_t)s.lplan[i];
+    const unsigned long long* ct = s.h_out + s.counters_off + 4 * (size_t)s.lplan[i];
     const bool on = c->opt_count_elements != 0;
     c->stats.launch_elements[i] = on ? (int64_t)ct[0] : -1;
     c->stats.launch_fetches[i] = on ? (int64_t)ct[1] : -1;
@@ -1501,7 +1589,7 @@ static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
   if (c->opt_count_elements) {
     int64_t t[4] = {0, 0, 0, 0};
     for (int i = 0; i < s.n_launch_plans; ++i)
-      for (int f = 0; f < 4; ++f) t[f] += (int64_t)s.h_res[s.counters_off + 4 * (size_t)i + f];
+      for (int f = 0; f < 4; ++f) t[f] += (int64_t)s.h_out[s.counters_off + 4 * (size_t)i + f];
     c->stats.elements = t[0];
     c->stats.list_fetches = t[1];
     c->stats.frontier_written = t[2];
@@ -1512,7 +1600,7 @@ static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
 
 // Run a synchronous group of queries on slot 0 (the user's stream).
 static gpm_status run_sync(gpm_ctx* c, JobPlanSet& js, std::vector<QueryWork>& qs,
-                           bool fission, uint64_t* outs) {
+                           bool fission, uint64_t* outs, const Arena* ar = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   Slot& s = c->slots[0];
   s.stream = c->user_stream;
@@ -1528,11 +1616,11 @@ static gpm_status run_sync(gpm_ctx* c, JobPlanSet& js, std::vector<QueryWork>& q
   }
   size_t used = 0;
   size_t budget = c->budget > c->serve_frontier_in_use ? c->budget - c->serve_frontier_in_use : 0;
-  gpm_status st = launch_group(c, s, js, fission, budget, &used);
+  gpm_status st = launch_group(c, s, js, fission, budget, &used, ar);
   if (st) return st;
   st = finish_sync(c, s);
   if (st) return st;
-  for (size_t i = 0; i < qs.size(); ++i) finish_query(qs[i], s.h_res, outs + 6 * i);
+  for (size_t i = 0; i < qs.size(); ++i) finish_query(qs[i], s.h_out, outs + 6 * i);
   c->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return GPM_OK;
 }
@@ -1658,7 +1746,7 @@ static gpm_status progress(gpm_ctx* c) {
       }
       for (auto& qw : s.queries) {
         uint64_t r[6];
-        finish_query(qw, s.h_res, r);
+        finish_query(qw, s.h_out, r);
         complete(c, qw.ticket, GPM_OK, "", r);
       }
       s.zero_dirty = false;
@@ -1893,6 +1981,17 @@ gpm_status gpm_create(gpm_ctx** out, int device, void* hip_stream, size_t hbm_bu
   }
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : freeb / 10 * 9;
   c->slots[0].stream = c->user_stream;
+  // the allocation-free count: this device's scratch address (looked up once
+  // per device, the device current), the synchronous slot's events, and host
+  // staging reserved now so that the call itself allocates nothing
+  if (scratch_address(device, &c->scratch) != 0 ||
+      slot_init(c, c->slots[0], c->user_stream) != GPM_OK) {
+    slot_free(c->slots[0]);
+    delete c;
+    return GPM_E_DEVICE;
+  }
+  c->na_stage.resize(kNoallocStageBytes);
+  c->na_res.resize(kNoallocResultWords);
   *out = c;
   return GPM_OK;
 }
@@ -2175,6 +2274,43 @@ gpm_status gpm_count(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern, i
   c->tuned[key] = cfg;
   restore();
   *count_out = ref;
+  return GPM_OK;
+}
+
+gpm_status gpm_count_noalloc(gpm_ctx* c, int32_t graph_id, const gpm_pattern* pattern,
+                             int mode, uint64_t* count_out) {
+  if (!c || !pattern || !count_out) return GPM_E_INVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (!c->scratch) return fail(c, GPM_E_DEVICE, "no device scratch");
+  gpm_query q{};
+  q.graph_id = graph_id;
+  q.kind = GPM_QUERY_COUNT;
+  q.mode_or_k = mode;
+  q.pattern = *pattern;
+  // the knob values the autotuner chose for this triple, as gpm_count uses them
+  std::vector<std::pair<int64_t*, int64_t>> saved;
+  if (c->opt_autotune) {
+    auto it = c->tuned.find(tune_key(graph_id, *pattern, mode));
+    if (it != c->tuned.end())
+      for (auto& kv : it->second) {
+        int64_t* k = knob(c, kv.first);
+        saved.push_back({k, *k});
+        *k = kv.second;
+      }
+  }
+  c->noalloc = true;
+  JobPlanSet js;
+  std::vector<QueryWork> qs(1);
+  gpm_status st = build_query(c, q, js, qs[0]);
+  uint64_t out[6];
+  if (!st) {
+    const Arena ar{(char*)c->scratch, kScratchBytes};
+    st = run_sync(c, js, qs, true, out, &ar);
+  }
+  c->noalloc = false;
+  for (auto& sv : saved) *sv.first = sv.second;
+  if (st) return st;
+  *count_out = out[0];
   return GPM_OK;
 }
 

@@ -41,6 +41,7 @@ EXPORTS = [
     "gpm_pattern_named", "gpm_pattern_from_edges", "gpm_plan", "gpm_frontier_waves",
     "gpm_count", "gpm_motifs", "gpm_count_batch", "gpm_submit", "gpm_poll", "gpm_wait",
     "gpm_inflight", "gpm_validate_csr", "gpm_prepare", "gpm_list", "gpm_serve_state",
+    "gpm_count_noalloc",
 ]
 
 
@@ -141,6 +142,7 @@ def lib():
         L.gpm_plan.argtypes = [P(Pattern), ctypes.c_int, P(PlanInfo)]
         L.gpm_frontier_waves.argtypes = [c_i64, c_i32, c_i64, c_i64, c_i64, P(c_i64)]
         L.gpm_count.argtypes = [c_vp, c_i32, P(Pattern), ctypes.c_int, P(c_u64)]
+        L.gpm_count_noalloc.argtypes = [c_vp, c_i32, P(Pattern), ctypes.c_int, P(c_u64)]
         L.gpm_motifs.argtypes = [c_vp, c_i32, ctypes.c_int, P(c_u64), c_sz]
         L.gpm_list.argtypes = [c_vp, c_i32, P(Pattern), ctypes.c_int, c_vp, c_i64, P(c_u64)]
         L.gpm_count_batch.argtypes = [c_vp, c_i32, P(Query), P(c_u64)]
@@ -337,6 +339,15 @@ class Context:
         out = c_u64()
         p = as_pattern(pattern)
         self._ck(lib().gpm_count(self._h, graph_id, ctypes.byref(p), mode, ctypes.byref(out)))
+        return out.value
+
+    def count_noalloc(self, graph_id: int, pattern, mode: int = GPM_VERTEX_INDUCED) -> int:
+        """gpm_count_noalloc: the count with no allocation (the graph must be
+        prepared for the query by an earlier count)."""
+        out = c_u64()
+        p = as_pattern(pattern)
+        self._ck(lib().gpm_count_noalloc(self._h, graph_id, ctypes.byref(p), mode,
+                                         ctypes.byref(out)))
         return out.value
 
     def list(self, graph_id: int, pattern, out, mode: int = GPM_VERTEX_INDUCED) -> int:
