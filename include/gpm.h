@@ -108,8 +108,11 @@ typedef struct {
                                 plan, 1<<3 per-edge motif terms, 1<<4
                                 per-vertex motif terms, 1<<5 local-graph
                                 cliques (one wave per root), 1<<6 4-cycle
-                                wedges, 1<<7 local-graph cliques (one
-                                workgroup per root; its own kernel)          */
+                                wedge aggregation (one workgroup per task;
+                                its own kernel), 1<<7 local-graph cliques
+                                (one workgroup per root; its own kernel),
+                                1<<8 per-edge terms from triangle counters,
+                                1<<9 triangle scatter                        */
     double launch_ms[GPM_MAX_LAUNCH_STATS];        /* duration (HIP events)   */
     int64_t launch_elements[GPM_MAX_LAUNCH_STATS]; /* as the totals above, per */
     int64_t launch_fetches[GPM_MAX_LAUNCH_STATS];  /* launch (-1 unless       */
@@ -163,24 +166,27 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     4- and 5-cliques per workgroup) into sub-tasks
  *   "leaf_cap"        generic DFS: last-level candidates whose leaf set is
  *                     at most this long are counted one per lane (0 = off)
- *   "cycle4_algo"     edge-induced 4-cycles: 0/2 wedge aggregation, 1 the
- *                     DFS plan (identical counts)
+ *   "cycle4_algo"     edge-induced 4-cycles: 0/2 wedge aggregation in LDS
+ *                     (one workgroup per task), 1 the DFS plan (identical
+ *                     counts)
+ *   "cycle4_mode"     wedge aggregation tasks: 0 (default) a cost model picks
+ *                     per root between direct id windows and hash tasks, 1
+ *                     hash tasks only, 2 direct windows for every root with
+ *                     more than "cycle4_batch" wedges (identical counts)
+ *   "cycle4_batch"    wedges per 4-cycle hash task (2..2^30, default 8192);
+ *                     a task whose distinct endpoints overflow the LDS table
+ *                     splits on the device (identical counts)
  *   "decompose"       1 (default) = wedge, 3-star, 4-path, tailed-triangle
  *                     and diamond counts (both modes) come from per-vertex
  *                     and per-edge terms (plus the 4-clique, triangle or
  *                     4-cycle count their induced forms need: counting-only
  *                     pruning, Sec. 5.4 (1)); 0 = the DFS plan (identical
  *                     counts)
- *   "wedge_mem"       bytes of device memory the 4-cycle counter arrays may
- *                     use (default 16 GiB; fewer waves when exceeded)
  *   "edge_terms"      per-edge motif terms (4-motifs, decomposed counts):
  *                     0 (default) = the k = 3 local-graph search adds each
  *                     triangle to its three edges' counters, then one pass
  *                     over the edges; 1 = one list intersection per edge
  *                     (identical counts)
- *   "wedge_list"      distinct wedge endpoints a 4-cycle task lists for its
- *                     second pass (64..2^24, default 2^19); a task with more
- *                     walks its wedges twice instead (identical counts)
  *   "budget"          device memory budget in bytes (as in gpm_create)
  *   "max_batch", "serve_slots", "max_pending", "serve_light_ms"   serving
  *                     limits (see gpm_submit)

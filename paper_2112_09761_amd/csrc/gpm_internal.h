@@ -52,7 +52,8 @@ enum JobKind : int32_t {
   kJobEdgeTri = 3,     // per-edge triangle counts and the 4-motif edge terms
   kJobVertexDeg = 4,   // per-vertex degree terms
   kJobCliqueLgs = 5,   // k-clique (k = 3..5) by local graph search with bitmaps
-  kJobCycleWedge = 6,  // edge-induced 4-cycles by wedge aggregation
+  kJobCycleBlock = 6,  // edge-induced 4-cycles by wedge aggregation in LDS, one
+                       // workgroup per task (own kernel)
   kJobCliqueLgsBlock = 7,  // k-clique (k = 3..5): the local graph of one large
                            // root shared by a whole workgroup (own kernel)
   kJobEdgeTerms = 8,   // per-edge motif terms from per-edge triangle counts
@@ -65,13 +66,13 @@ constexpr uint32_t kKindDfs = 1u << kJobDfs;
 constexpr uint32_t kKindEdgeTri = 1u << kJobEdgeTri;
 constexpr uint32_t kKindVertexDeg = 1u << kJobVertexDeg;
 constexpr uint32_t kKindCliqueLgs = 1u << kJobCliqueLgs;
-constexpr uint32_t kKindCycleWedge = 1u << kJobCycleWedge;
+constexpr uint32_t kKindCycleBlock = 1u << kJobCycleBlock;
 constexpr uint32_t kKindCliqueLgsBlock = 1u << kJobCliqueLgsBlock;
 constexpr uint32_t kKindEdgeTerms = 1u << kJobEdgeTerms;
 constexpr uint32_t kKindTriScatter = 1u << kJobTriScatter;
 // kinds of the per-wave persistent kernel (the workgroup kernel has its own)
 constexpr uint32_t kKindAll = kKindClique | kKindDfs | kKindEdgeTri | kKindVertexDeg |
-                              kKindCliqueLgs | kKindCycleWedge | kKindEdgeTerms |
+                              kKindCliqueLgs | kKindEdgeTerms |
                               kKindTriScatter;
 constexpr int kLgsMaxVertices = 2048;   // local graphs handled by the bitmap kernel
 constexpr int kBlockWaves = 16;         // workgroup of the large-root kernel (1024 threads)
@@ -82,6 +83,31 @@ constexpr int kLgsBlockMaxVertices = kBlockWaves * 64;  // one vertex per thread
 constexpr int kSortBatch = 512;
 constexpr int kSortWords = kSortBatch + 64;
 constexpr int kBlockSortWords = kBlockWaves * kSortWords;
+
+// 4-cycle workgroup kernel (kJobCycleBlock): 1024 threads, a table of
+// kCycTableWords words of LDS.  Direct windows count the endpoints of one id
+// window in 16-bit counters packed two per word (kCycWindow ids), or in
+// 32-bit counters (half the ids) for roots with 65535 or more lower
+// neighbours.  Hash tasks use the table as keys | counts (kCycSlots each);
+// a task stops and splits once kCycHashCap distinct keys are in.
+constexpr int kCycWaves = 16;
+constexpr int kCycTableWords = 32768;
+constexpr int kCycWindow = 2 * kCycTableWords;
+constexpr int kCycSlots = kCycTableWords / 2;
+constexpr int kCycHashCap = kCycSlots * 3 / 4;
+constexpr int kCycStack = 64;   // pending split tasks per workgroup
+
+// A task of the 4-cycle kernel, 4 int32 words.  head >= 0: direct windows of
+// root v = head: windows a .. a+b-1 (window i covers ids [i*W, (i+1)*W) below
+// v; W = kCycWindow, or kCycWindow / 2 when c & 1: 32-bit counters).
+// head < 0: hash task over the roots r[-head-1 .. a) of the job's root list
+// (task_dst) with endpoints in [b, c) (and below each root).
+struct CycTask {
+  int32_t head;
+  int32_t a;
+  int32_t b;
+  int32_t c;
+};
 
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
 // root tasks) triple with its own result slot.
@@ -110,6 +136,8 @@ struct Job {
   unsigned int* tri;       // the group's per-DAG-edge counters (set at launch;
                            // zero between launches)
   const int64_t* deg_rp;   // kJobEdgeTerms: offsets of the symmetric graph (degrees)
+  int32_t n_vertices;      // kJobCycleBlock: vertices of the graph (hash keys)
+  int32_t pad_;
 };
 
 struct KernelArgs {
@@ -126,10 +154,9 @@ struct KernelArgs {
   int64_t wave_stride;             // int32 words of fbuf per wave
   int32_t lds_words;               // int32 words of dynamic LDS per wave
   int32_t lgs_tile;                // local graphs up to this size use LDS
-  int32_t zlist;                   // words at the end of each zbuf region: the
-                                   // list of a wedge task's distinct endpoints
-  unsigned int* zbuf;              // per-wave counter arrays, zero between tasks
-  int64_t zstride;                 // words of zbuf per wave (counters, then the list)
+  int32_t pad0;
+  int32_t* zbuf;                   // 4-cycle kernel: per-workgroup cursor regions
+  int64_t zstride;                 // words of zbuf per workgroup
 };
 
 // Local-graph tile of T vertices, in int32 words: L[T] | P[T + 1] | (pad to
@@ -182,6 +209,10 @@ int launch_persistent(uint32_t kinds, bool count_elems, const KernelArgs& a,
                       int blocks, size_t lds_bytes, void* stream);
 int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max_blocks,
                      size_t lds_bytes, void* stream);
+// The 4-cycle workgroup kernel; *blocks_out receives the grid size (one
+// cursor region of a.zstride words per workgroup in a.zbuf).
+int cycle_block_grid(int cus, int64_t max_blocks, int* blocks_out);
+int launch_cycle_block(bool count_elems, const KernelArgs& a, int blocks, void* stream);
 int launch_list(const ListArgs& a, int blocks, void* stream);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
 

@@ -864,83 +864,6 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// edge-induced 4-cycles by wedge aggregation (counting only; the paper's
-// counting-only pruning of Sec. 5.4 (1) applied to the 4-cycle).  On the
-// graph relabelled by ascending degree, every 4-cycle is counted once at its
-// largest vertex v together with the vertex w opposite v: with c_w the number
-// of wedges v-u-w (u, w < v), the root contributes sum_w C(c_w, 2).  Each wave
-// owns a zero-initialised counter array `cnt` (one word per vertex): pass 1
-// adds the wedges, pass 2 walks them again, takes each counter with an
-// atomic exchange (restoring zero) and adds C(c, 2) once per distinct w.
-// Sub-task (v, [a, b)) only counts endpoints w in [a, b), so a heavy root is
-// split across waves without any cross-task aggregation.
-// ---------------------------------------------------------------------------
-
-// One walk over the wedges v-u-w of a root (u over Nlo[0..e), w over the part
-// of N(u) in [a, b)).  The out-list offsets of each batch of 64 u's are staged
-// in S and their lengths' prefix in PF (LDS), so a wedge costs one search of
-// PF and one load of col.
-// Pass 1 (!SECOND): cnt[w] += 1; an endpoint seen for the first time is
-// appended to `list` (capacity cap); returns the number of distinct
-// endpoints (uniform; may exceed cap).
-// Pass 2 (SECOND, used when the list overflowed): takes every counter with an
-// atomic exchange (restoring zero) and returns Σ C(c_w, 2) (per lane).
-template <bool SECOND>
-__device__ __forceinline__ uint64_t wedge_pass(const int64_t* __restrict__ rp,
-                                               const int32_t* __restrict__ col,
-                                               const int32_t* Nlo, int32_t e, int32_t a,
-                                               int32_t b, unsigned int* cnt, int32_t* list,
-                                               int32_t cap, int64_t* S, int32_t* PF) {
-  const int l = lane_id();
-  uint64_t c = 0;
-  for (int32_t ub = 0; ub < e; ub += 64) {
-    const int32_t i = ub + l;
-    int32_t len = 0;
-    int64_t start = 0;
-    if (i < e) {
-      const int32_t u = Nlo[i];
-      const int64_t s0 = rp[u];
-      const int32_t* Nu = col + s0;
-      const int32_t du = (int32_t)(rp[u + 1] - s0);
-      const int32_t lo = lower_bound(Nu, du, a);
-      len = lower_bound(Nu, du, b) - lo;
-      start = s0 + lo;
-    }
-    const int32_t incl = wave_incl_scan(len);
-    S[l] = start;
-    PF[l] = incl;
-    wave_sync_mem();
-    const int32_t tot = uni(__shfl(incl, 63, 64));
-    for (int32_t tb = 0; tb < tot; tb += 64) {
-      const int32_t t = tb + l;
-      bool fresh = false;
-      int32_t w = 0;
-      if (t < tot) {
-        const int32_t o = upper_bound(PF, 64, t);
-        const int32_t r = t - (o > 0 ? PF[o - 1] : 0);
-        w = col[S[o] + r];
-        if (!SECOND) {
-          fresh = atomicAdd(&cnt[w], 1u) == 0u;
-        } else {
-          const uint64_t x = (uint64_t)atomicExch(&cnt[w], 0u);
-          c += x * (x - (x ? 1 : 0)) / 2;
-        }
-      }
-      if (!SECOND) {
-        const uint64_t m = wave_ballot(fresh);
-        if (fresh) {
-          const uint64_t p = c + lanes_below(m);
-          if (p < (uint64_t)cap) list[p] = w;
-        }
-        c += (uint64_t)__popcll(m);
-      }
-    }
-    wave_sync_mem();
-  }
-  return c;
-}
-
-// ---------------------------------------------------------------------------
 // generic plan-driven DFS (Alg. 1 generalised by the plan table)
 // ---------------------------------------------------------------------------
 
@@ -1605,7 +1528,6 @@ gpm_persistent(KernelArgs a) {
   extern __shared__ int32_t lds[];
   __shared__ int32_t lds_state[kWavesPerBlock][2 * kMaxK];
   __shared__ int32_t dfs_defq[(KINDS & kKindDfs) ? kWavesPerBlock : 1][64];
-  __shared__ long long wedge_lds[(KINDS & kKindCycleWedge) ? kWavesPerBlock : 1][96];
   const int w = threadIdx.x >> 6;
   int32_t* my = lds + (size_t)w * a.lds_words;
   int32_t* st_words = lds_state[w];
@@ -1676,46 +1598,6 @@ gpm_persistent(KernelArgs a) {
           lgs_tasks<CE, false>(J, a, my, fb, t0, t1, acc, ec);
       } else {
         lgs_tasks<CE, false>(J, a, my, fb, t0, t1, acc, ec);
-      }
-    } else if ((KINDS & kKindCycleWedge) && kind == kJobCycleWedge) {
-      nf = 1;
-      unsigned int* cnt = a.zbuf + gw * a.zstride;
-      // the wave's region ends with its list of distinct endpoints
-      int32_t* list = (int32_t*)(cnt + a.zstride - a.zlist);
-      for (int64_t t = t0; t < t1; ++t) {
-        const int32_t v = uni(J.task_src[t]);
-        int32_t part = 0, parts = 1;
-        if (J.task_dst) {
-          const int32_t enc = uni(J.task_dst[t]);
-          part = enc & 0xffff;
-          parts = enc >> 16;
-        }
-        const int32_t* Nv = col + rp[v];
-        const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
-        const int32_t a0 = (int32_t)((int64_t)v * part / parts);
-        const int32_t b0 = (int32_t)((int64_t)v * (part + 1) / parts);
-        int64_t* S = (int64_t*)wedge_lds[w];
-        int32_t* PF = (int32_t*)(wedge_lds[w] + 64);
-        const int64_t nd =
-            uni64((int64_t)wedge_pass<false>(rp, col, Nv, e, a0, b0, cnt, list, a.zlist, S, PF));
-        // every counter update and list entry of pass 1 completes before pass 2 reads it
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        // pass 2; counters and list entries end at zero: the whole region is
-        // zero between tasks, whatever layout the next launch gives it
-        if (nd <= (int64_t)a.zlist) {
-          // over the distinct endpoints only
-          for (int64_t q = lane_id(); q < nd; q += 64) {
-            const uint64_t x = (uint64_t)atomicExch(&cnt[list[q]], 0u);
-            list[q] = 0;
-            acc[0] += x * (x - (x ? 1 : 0)) / 2;
-          }
-        } else {
-          acc[0] += wedge_pass<true>(rp, col, Nv, e, a0, b0, cnt, list, a.zlist, S, PF);
-          for (int32_t q = lane_id(); q < a.zlist; q += 64) list[q] = 0;
-        }
-        if (CE) {
-          ec.fetches += (uint64_t)e * 64;
-        }
       }
     } else if ((KINDS & kKindDfs) && kind == kJobDfs) {
       nf = 1;
@@ -1870,6 +1752,305 @@ gpm_lgs_block(KernelArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// edge-induced 4-cycles by wedge aggregation in LDS (the counting-only pruning
+// of Sec. 5.4 (1) applied to the 4-cycle).  On the graph relabelled by
+// ascending (degree, id), every 4-cycle is counted once at its largest vertex
+// v together with the vertex w opposite v: with c_w the number of wedges
+// v-u-w (u, w < v), the root contributes sum_w C(c_w, 2).  One workgroup
+// counts the wedges of one task in a table in its LDS:
+//  - direct windows (roots whose endpoints are dense among the ids below
+//    them): one counter per endpoint id of a window; each lane keeps its
+//    position in N(u) (its cursor, in the workgroup's HBM region) from one
+//    window of the task to the next, so a window costs one search per u;
+//  - hash tasks (light roots batched, or an id range of one root): keys
+//    slot * n + w + 1 with their counts; a task that meets more distinct keys
+//    than kCycHashCap stops, splits (its roots in halves, else its id range
+//    in halves) and runs again.
+// Every phase leaves the table at zero.
+// ---------------------------------------------------------------------------
+
+static_assert(kCycSlots == (1 << 14), "hash of the 4-cycle table assumes 2^14 slots");
+static_assert(kCycWindow == 65536, "16-bit window counters assume 65536 ids");
+
+struct CycShared {
+  int64_t S[kCycWaves][64];     // per wave: list start of each lane's slice
+  int32_t PF[kCycWaves][64];    // per wave: inclusive prefix of the slice lengths
+  int32_t stack[kCycStack][4];  // hash tasks still to run: (r0, r1, x, y)
+  int32_t sp;
+  uint32_t distinct;            // keys in the table
+  int32_t overflow;             // the running hash task split
+  long long chunk;
+};
+
+__device__ __forceinline__ uint32_t cyc_hash(uint32_t key) {
+  return (key * 2654435761u) >> 18;
+}
+
+// One batch of up to 64 slices per wave: lane l holds the slice
+// col[start, start + len); the wave takes the slices' elements 64 at a time
+// (each lane finds its slice in the staged prefix) and hands each to sink.
+template <bool CE, typename Sink>
+__device__ __forceinline__ void cyc_batch(const int32_t* __restrict__ col, int64_t start,
+                                          int32_t len, int64_t* S, int32_t* PF,
+                                          ElemCounter& ec, Sink&& sink) {
+  const int l = lane_id();
+  const int32_t incl = wave_incl_scan(len);
+  S[l] = start;
+  PF[l] = incl;
+  wave_sync_mem();
+  const int32_t tot = uni(__shfl(incl, 63, 64));
+  for (int32_t tb = 0; tb < tot; tb += 64) {
+    const int32_t t = tb + l;
+    if (t < tot) {
+      const int32_t o = upper_bound(PF, 64, t);
+      const int32_t r = t - (o > 0 ? PF[o - 1] : 0);
+      sink(col[S[o] + r]);
+    }
+  }
+  if (CE) ec.elems += (uint64_t)tot;
+  wave_sync_mem();
+}
+
+// Direct windows a .. a+b-1 of root v (see CycTask).
+template <bool CE>
+__device__ __forceinline__ void cyc_direct(const int64_t* __restrict__ rp,
+                                           const int32_t* __restrict__ col, const CycTask& T,
+                                           uint32_t* tab, int32_t* cursor, CycShared& sh,
+                                           uint64_t& acc, ElemCounter& ec) {
+  const int32_t v = T.head;
+  const bool c32 = (T.c & 1) != 0;
+  const int64_t W = c32 ? kCycWindow / 2 : kCycWindow;
+  const int32_t* Nv = col + rp[v];
+  const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
+  const int wv = (int)(threadIdx.x >> 6);
+  const int l = lane_id();
+  for (int32_t k = T.a; k < T.a + T.b; ++k) {
+    const int64_t wa64 = (int64_t)k * W;
+    if (wa64 >= v) break;
+    const int32_t wa = (int32_t)wa64;
+    const int32_t wb = (int32_t)min(wa64 + W, (int64_t)v);
+    for (int32_t ub = wv * 64; ub < e; ub += kCycWaves * 64) {
+      const int32_t i = ub + l;
+      int64_t start = 0;
+      int32_t len = 0;
+      if (i < e) {
+        const int32_t u = Nv[i];
+        const int64_t s0 = rp[u];
+        const int32_t du = (int32_t)(rp[u + 1] - s0);
+        const int32_t lo = (k == T.a) ? lower_bound(col + s0, du, wa) : cursor[i];
+        const int32_t hi = lo + lower_bound(col + s0 + lo, du - lo, wb);
+        cursor[i] = hi;
+        start = s0 + lo;
+        len = hi - lo;
+      }
+      if (CE) ec.fetches += (uint64_t)min(64, e - ub);
+      if (c32) {
+        cyc_batch<CE>(col, start, len, sh.S[wv], sh.PF[wv], ec,
+                      [&](int32_t w) { atomicAdd(&tab[w - wa], 1u); });
+      } else {
+        cyc_batch<CE>(col, start, len, sh.S[wv], sh.PF[wv], ec, [&](int32_t w) {
+          const uint32_t x = (uint32_t)(w - wa);
+          atomicAdd(&tab[x >> 1], (x & 1u) ? 0x10000u : 1u);
+        });
+      }
+    }
+    __syncthreads();
+    // sum_w C(c_w, 2) over the window; the table back to zero
+    const int32_t words = c32 ? (wb - wa) : ((wb - wa + 1) >> 1);
+    for (int32_t q = (int32_t)threadIdx.x; q < words; q += kCycWaves * 64) {
+      const uint32_t x = tab[q];
+      if (x) {
+        tab[q] = 0;
+        if (c32) {
+          acc += (uint64_t)x * (uint64_t)(x - 1) / 2;
+        } else {
+          const uint64_t c0 = x & 0xffffu, c1 = x >> 16;
+          acc += c0 * (c0 ? c0 - 1 : 0) / 2 + c1 * (c1 ? c1 - 1 : 0) / 2;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Hash task over roots[r0, r1) with endpoints in [x, y), splitting on overflow.
+template <bool CE>
+__device__ __forceinline__ void cyc_hash_task(const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ roots, uint32_t n,
+                                              const CycTask& T, uint32_t* tab, CycShared& sh,
+                                              uint64_t& acc, ElemCounter& ec) {
+  uint32_t* keys = tab;
+  uint32_t* cnts = tab + kCycSlots;
+  const int wv = (int)(threadIdx.x >> 6);
+  const int l = lane_id();
+  if (threadIdx.x == 0) {
+    sh.stack[0][0] = -T.head - 1;
+    sh.stack[0][1] = T.a;
+    sh.stack[0][2] = T.b;
+    sh.stack[0][3] = T.c;
+    sh.sp = 1;
+  }
+  __syncthreads();
+  for (;;) {
+    const int32_t sp = uni(sh.sp);
+    if (sp == 0) break;
+    const int32_t r0 = uni(sh.stack[sp - 1][0]);
+    const int32_t r1 = uni(sh.stack[sp - 1][1]);
+    const int32_t x = uni(sh.stack[sp - 1][2]);
+    const int32_t y = uni(sh.stack[sp - 1][3]);
+    __syncthreads();  // every wave has read the entry before it is popped
+    if (threadIdx.x == 0) {
+      sh.sp = sp - 1;
+      sh.distinct = 0;
+      sh.overflow = 0;
+    }
+    __syncthreads();
+    const int32_t nr = r1 - r0;
+    const bool one = nr == 1;
+    for (int32_t rr = r0 + (one ? 0 : wv); rr < r1; rr += (one ? 1 : kCycWaves)) {
+      if (__hip_atomic_load(&sh.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+      const int32_t v = uni(roots[rr]);
+      const uint32_t base = (uint32_t)(rr - r0) * n + 1u;
+      const int32_t hy = min(y, v);
+      const int32_t* Nv = col + rp[v];
+      const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
+      for (int32_t ub = one ? wv * 64 : 0; ub < e; ub += one ? kCycWaves * 64 : 64) {
+        if (uni(__hip_atomic_load(&sh.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)))
+          break;
+        const int32_t i = ub + l;
+        int64_t start = 0;
+        int32_t len = 0;
+        if (i < e && x < hy) {
+          const int32_t u = Nv[i];
+          const int64_t s0 = rp[u];
+          const int32_t du = (int32_t)(rp[u + 1] - s0);
+          const int32_t lo = lower_bound(col + s0, du, x);
+          len = lower_bound(col + s0 + lo, du - lo, hy);
+          start = s0 + lo;
+        }
+        if (CE) ec.fetches += (uint64_t)min(64, e - ub);
+        cyc_batch<CE>(col, start, len, sh.S[wv], sh.PF[wv], ec, [&](int32_t w) {
+          // after a split at most one insert per thread follows: the table
+          // never fills (kCycHashCap + 1024 < kCycSlots), so probing ends
+          if (__hip_atomic_load(&sh.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+          const uint32_t key = base + (uint32_t)w;
+          uint32_t h = cyc_hash(key);
+          for (;;) {
+            const uint32_t old = atomicCAS(&keys[h], 0u, key);
+            if (old == 0u) {
+              if (atomicAdd(&sh.distinct, 1u) + 1u > (uint32_t)kCycHashCap)
+                __hip_atomic_store(&sh.overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              atomicAdd(&cnts[h], 1u);
+              break;
+            }
+            if (old == key) {
+              atomicAdd(&cnts[h], 1u);
+              break;
+            }
+            h = (h + 1u) & (uint32_t)(kCycSlots - 1);
+          }
+        });
+      }
+    }
+    __syncthreads();
+    if (uni(sh.overflow)) {
+      for (int32_t q = (int32_t)threadIdx.x; q < kCycTableWords; q += kCycWaves * 64) tab[q] = 0;
+      if (threadIdx.x == 0) {
+        // run the halves next (depth <= log2 roots + log2 ids: within kCycStack)
+        int32_t t = sh.sp;
+        if (nr > 1) {
+          const int32_t mid = r0 + nr / 2;
+          sh.stack[t][0] = mid; sh.stack[t][1] = r1; sh.stack[t][2] = x; sh.stack[t][3] = y;
+          ++t;
+          sh.stack[t][0] = r0; sh.stack[t][1] = mid; sh.stack[t][2] = x; sh.stack[t][3] = y;
+          ++t;
+        } else {
+          const int32_t hy = min(y, roots[r0]);
+          const int32_t mid = x + (hy - x) / 2;
+          sh.stack[t][0] = r0; sh.stack[t][1] = r1; sh.stack[t][2] = mid; sh.stack[t][3] = hy;
+          ++t;
+          sh.stack[t][0] = r0; sh.stack[t][1] = r1; sh.stack[t][2] = x; sh.stack[t][3] = mid;
+          ++t;
+        }
+        sh.sp = t;
+      }
+      __syncthreads();
+      continue;
+    }
+    // sum over the keys of C(count, 2); the table back to zero
+    for (int32_t q = (int32_t)threadIdx.x; q < kCycSlots; q += kCycWaves * 64) {
+      if (keys[q]) {
+        const uint64_t c = cnts[q];
+        acc += c * (c - 1) / 2;
+        keys[q] = 0;
+        cnts[q] = 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Persistent workgroup kernel of the 4-cycle tasks: wave 0 pops a chunk of
+// tasks from the per-XCD queues and shares it through LDS.
+template <bool CE>
+__global__ void __launch_bounds__(kCycWaves * 64)
+gpm_cycle_block(KernelArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t cyc_tab[];
+  __shared__ CycShared sh;
+  for (int32_t q = (int32_t)threadIdx.x; q < kCycTableWords; q += kCycWaves * 64) cyc_tab[q] = 0;
+  int32_t* cursor = a.zbuf + (int64_t)blockIdx.x * a.zstride;
+  const int home = (int)(blockIdx.x & (kQueues - 1));
+  uint32_t dead = 0;
+  int cur = -1;
+  int cur_slot = 0;
+  uint64_t acc[1] = {0};
+  ElemCounter ec;
+  for (;;) {
+    if (threadIdx.x < 64) {
+      const int64_t c = pop_chunk(a.queue_cnt, a.queue_begin, home, dead);
+      if (lane_id() == 0) sh.chunk = c;
+    }
+    __syncthreads();
+    const int64_t c = uni64(sh.chunk);
+    __syncthreads();  // read by every wave before wave 0 pops again
+    if (c < 0) break;
+    const int j = uni(find_job(a.job_chunk_begin, a.n_jobs, c));
+    if (j != cur) {
+      if (cur >= 0) flush(a.results, cur_slot, acc, 1);
+      cur = j;
+    }
+    const Job& J = a.jobs[j];
+    cur_slot = J.slot;
+    const CycTask* tasks = (const CycTask*)J.task_src;
+    const int64_t t0 = (c - a.job_chunk_begin[j]) * (int64_t)J.chunk;
+    const int64_t t1 = min(t0 + (int64_t)J.chunk, J.n_tasks);
+    for (int64_t t = t0; t < t1; ++t) {
+      CycTask T;
+      T.head = uni(tasks[t].head);
+      T.a = uni(tasks[t].a);
+      T.b = uni(tasks[t].b);
+      T.c = uni(tasks[t].c);
+      if (T.head >= 0)
+        cyc_direct<CE>(J.rp, J.col, T, cyc_tab, cursor, sh, acc[0], ec);
+      else
+        cyc_hash_task<CE>(J.rp, J.col, J.task_dst, (uint32_t)J.n_vertices, T, cyc_tab, sh,
+                          acc[0], ec);
+    }
+  }
+  if (cur >= 0) flush(a.results, cur_slot, acc, 1);
+  if (CE) {
+    uint64_t e = wave_sum_u64(ec.elems);
+    uint64_t f = wave_sum_u64(ec.fetches);
+    if (lane_id() == 0) {
+      atomicAdd(&a.counters[0], (unsigned long long)e / 64ull);
+      atomicAdd(&a.counters[1], (unsigned long long)f / 64ull);
+    }
+  }
+}
+
 __global__ void fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -1895,7 +2076,6 @@ static hipError_t launch_kinds(uint32_t kinds, const KernelArgs& a, int blocks, 
     case kKindEdgeTri: return launch_t<kKindEdgeTri, CE>(a, blocks, lds, s);
     case kKindVertexDeg: return launch_t<kKindVertexDeg, CE>(a, blocks, lds, s);
     case kKindCliqueLgs: return launch_t<kKindCliqueLgs, CE>(a, blocks, lds, s);
-    case kKindCycleWedge: return launch_t<kKindCycleWedge, CE>(a, blocks, lds, s);
     case kKindEdgeTerms: return launch_t<kKindEdgeTerms, CE>(a, blocks, lds, s);
     case kKindTriScatter: return launch_t<kKindTriScatter, CE>(a, blocks, lds, s);
     case kKindCliqueLgs | kKindClique:
@@ -1928,6 +2108,31 @@ int launch_lgs_block(bool count_elems, const KernelArgs& a, int cus, int64_t max
     hipLaunchKernelGGL(gpm_lgs_block<true>, dim3((unsigned)blocks), dim3(kBlockWaves * 64), lds_bytes, s, a);
   else
     hipLaunchKernelGGL(gpm_lgs_block<false>, dim3((unsigned)blocks), dim3(kBlockWaves * 64), lds_bytes, s, a);
+  return (int)hipGetLastError();
+}
+
+static constexpr size_t kCycLdsBytes = (size_t)kCycTableWords * 4;
+
+int cycle_block_grid(int cus, int64_t max_blocks, int* blocks_out) {
+  const void* f = (const void*)gpm_cycle_block<false>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCycLdsBytes);
+  if (e != hipSuccess) return (int)e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kCycWaves * 64, kCycLdsBytes);
+  if (e != hipSuccess) return (int)e;
+  *blocks_out = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), max_blocks));
+  return 0;
+}
+
+int launch_cycle_block(bool count_elems, const KernelArgs& a, int blocks, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const void* f = count_elems ? (const void*)gpm_cycle_block<true> : (const void*)gpm_cycle_block<false>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCycLdsBytes);
+  if (e != hipSuccess) return (int)e;
+  if (count_elems)
+    hipLaunchKernelGGL(gpm_cycle_block<true>, dim3((unsigned)blocks), dim3(kCycWaves * 64), kCycLdsBytes, s, a);
+  else
+    hipLaunchKernelGGL(gpm_cycle_block<false>, dim3((unsigned)blocks), dim3(kCycWaves * 64), kCycLdsBytes, s, a);
   return (int)hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -77,11 +78,13 @@ struct Graph {
   int32_t* ren_lo_dst = nullptr;
   int64_t ren_n_lo = 0;
   bool ren_ready = false;
-  // 4-cycle wedge-aggregation roots on the relabelled graph: (v, part | parts << 16)
-  int32_t* wedge_src = nullptr;
-  int32_t* wedge_dst = nullptr;
-  int64_t n_wedge = 0;
-  int64_t wedge_key = -1;
+  // 4-cycle tasks of the workgroup kernel on the relabelled graph (CycTask
+  // records) and the root list of its hash tasks
+  CycTask* cyc_tasks = nullptr;
+  int32_t* cyc_roots = nullptr;
+  int64_t n_cyc = 0;
+  int32_t cyc_max_e = 0;          // lower neighbours of the largest direct root (cursor words)
+  int64_t cyc_key = -1;
   int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
   int32_t* lo_dst = nullptr;
   int64_t n_lo = 0;
@@ -118,8 +121,7 @@ struct Slot {
   void* d_meta = nullptr;  size_t d_meta_bytes = 0;    // jobs, plans, offsets
   unsigned long long* d_res = nullptr; size_t d_res_words = 0;  // results + queues + counters
   int32_t* d_fbuf = nullptr; size_t d_fbuf_bytes = 0;
-  unsigned int* d_zero = nullptr; size_t d_zero_bytes = 0;  // wedge counters
-  bool zero_dirty = true;
+  int32_t* d_cursor = nullptr; size_t d_cursor_bytes = 0;  // 4-cycle cursor regions
   unsigned int* d_tri = nullptr; size_t d_tri_bytes = 0;    // per-edge triangle counters
   bool tri_dirty = true;
   void* h_stage = nullptr; size_t h_stage_bytes = 0;    // pinned
@@ -173,11 +175,11 @@ struct gpm_ctx {
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
   int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
   int64_t opt_decompose = 1;                    // counting-only decomposition of named motifs
-  int64_t opt_wedge_list = 1 << 19;             // distinct-endpoint list per 4-cycle wave
+  int64_t opt_cycle4_mode = 0;                  // 0 cost model, 1 hash tasks only, 2 direct windows
+  int64_t opt_cycle4_batch = 8192;              // wedges per 4-cycle hash task
   int64_t opt_edge_terms = 0;                   // 0 auto (triangle scatter), 1 per-edge intersection
   int lds_block_max = 65536;                    // dynamic LDS per workgroup (bytes)
   int64_t opt_tune_min_ms = 20;
-  int64_t opt_wedge_mem = int64_t(16) << 30;   // cap of the 4-cycle counter arrays
   // autotuner cache: (graph, pattern, mode) -> tuned knob values
   std::map<std::string, std::vector<std::pair<std::string, int64_t>>> tuned;
   bool tuning = false;
@@ -255,9 +257,10 @@ static void free_graph(Graph& g) {
   free_view(g.ren);
   dev_free(g.ren_ids);
   g.ren_ids = nullptr;
-  dev_free(g.wedge_src);
-  dev_free(g.wedge_dst);
-  g.wedge_src = g.wedge_dst = nullptr;
+  dev_free(g.cyc_tasks);
+  dev_free(g.cyc_roots);
+  g.cyc_tasks = nullptr;
+  g.cyc_roots = nullptr;
   dev_free(g.ren_lo_src);
   dev_free(g.ren_lo_dst);
   g.ren_lo_src = g.ren_lo_dst = nullptr;
@@ -526,55 +529,144 @@ static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
   return GPM_OK;
 }
 
-// Roots of the 4-cycle wedge aggregation on the relabelled graph, heaviest
-// first.  A root's work is at most sum over its lower neighbours u of d(u);
-// it gets ceil(work / share) disjoint endpoint ranges (share: a quarter of an
-// even split over `waves` waves).
-static gpm_status ensure_wedge(gpm_ctx* c, Graph& g, int64_t waves) {
+// Tasks of the 4-cycle workgroup kernel on the relabelled graph.  Root v
+// (the cycle's largest vertex) has e_v lower neighbours u and
+// E_v = sum_u |N(u) ∩ [0, v)| wedges; roots with fewer than two wedges hold no
+// 4-cycle.  A root goes to direct windows when counting every id below it
+// (v/2 counter words, 2 searches per u and window, one increment per wedge)
+// costs less than hashing its wedges (about 4 table operations per wedge);
+// direct roots are cut into parts of consecutive windows of about equal
+// share.  Other roots with more than `batch` wedges become hash tasks over id
+// ranges of about `batch` wedges each (the ranges follow the degree mass
+// rp[x], since a wedge ends at w about d_w times as often as at a degree-1
+// vertex); lighter roots are packed into hash tasks of up to `batch` wedges.
+static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
   gpm_status st = ensure_ren(c, g);
   if (st) return st;
-  if (g.wedge_key == waves) return GPM_OK;
+  const int64_t key = (c->opt_cycle4_mode << 40) ^ c->opt_cycle4_batch;
+  if (g.cyc_key == key) return GPM_OK;
   if (c->noalloc) return not_prepared(c);
-  dev_free(g.wedge_src);
-  dev_free(g.wedge_dst);
-  g.wedge_src = g.wedge_dst = nullptr;
+  dev_free(g.cyc_tasks);
+  dev_free(g.cyc_roots);
+  g.cyc_tasks = nullptr;
+  g.cyc_roots = nullptr;
   const HostCSR& R = g.ren_host;
+  const int64_t n = R.n;
+  std::vector<int32_t> ev(n, 0);
+  std::vector<int64_t> Ev(n, 0);
+  {
+    const int nt = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&, t]() {
+        for (int64_t v = t; v < n; v += nt) {
+          const int32_t* b = R.col.data() + R.rp[v];
+          const int32_t* e = R.col.data() + R.rp[v + 1];
+          const int64_t lo = std::lower_bound(b, e, (int32_t)v) - b;
+          int64_t w = 0;
+          for (int64_t p = 0; p < lo; ++p) {
+            const int32_t u = b[p];
+            const int32_t* ub = R.col.data() + R.rp[u];
+            const int32_t* ue = R.col.data() + R.rp[u + 1];
+            w += std::lower_bound(ub, ue, (int32_t)v) - ub;
+          }
+          ev[v] = (int32_t)lo;
+          Ev[v] = w;
+        }
+      });
+    for (auto& x : th) x.join();
+  }
+  const int64_t batch = c->opt_cycle4_batch;
+  struct Direct { int32_t v; int64_t E; };
+  std::vector<Direct> direct;
+  std::vector<std::pair<int64_t, int32_t>> ranged;  // (E, v)
+  std::vector<int32_t> light;
+  int64_t direct_total = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t E = Ev[v];
+    if (E < 2) continue;
+    const bool c32 = ev[v] >= 65535;
+    const int64_t W = c32 ? kCycWindow / 2 : kCycWindow;
+    const int64_t K = (v + W - 1) / W;
+    const double cost_direct = (c32 ? (double)v : v / 2.0) + 2.0 * ev[v] * K + (double)E;
+    const double cost_hash = 4.0 * (double)E;
+    const bool dir = c->opt_cycle4_mode == 2 ? E > batch
+                   : c->opt_cycle4_mode == 1 ? false
+                   : cost_direct < cost_hash;
+    if (dir) {
+      direct.push_back({(int32_t)v, E});
+      direct_total += E;
+    } else if (E > batch) {
+      ranged.push_back({E, (int32_t)v});
+    } else {
+      light.push_back((int32_t)v);
+    }
+  }
+  std::sort(direct.begin(), direct.end(), [](const Direct& a, const Direct& b) { return a.E > b.E; });
+  std::sort(ranged.begin(), ranged.end(), [](const std::pair<int64_t, int32_t>& a,
+                                             const std::pair<int64_t, int32_t>& b) {
+    return a.first > b.first;
+  });
+  std::vector<CycTask> tasks;
   std::vector<int32_t> roots;
-  std::vector<double> work;
-  double total = 0;
-  for (int64_t v = 0; v < R.n; ++v) {
-    int64_t e = std::lower_bound(R.col.begin() + R.rp[v], R.col.begin() + R.rp[v + 1], (int32_t)v) -
-                (R.col.begin() + R.rp[v]);
-    if (e < 2) continue;
-    double wk = 0;
-    for (int64_t p = R.rp[v]; p < R.rp[v] + e; ++p) {
-      int32_t u = R.col[p];
-      wk += (double)(R.rp[u + 1] - R.rp[u]);
-    }
-    roots.push_back((int32_t)v);
-    work.push_back(wk);
-    total += wk;
+  int32_t max_e = 0;
+  // direct roots: parts of consecutive windows, each about a quarter of an
+  // even share of the direct wedges over the workgroups
+  const int64_t share = std::max<int64_t>(direct_total / ((int64_t)c->cus * 4), int64_t(1) << 20);
+  for (const Direct& d : direct) {
+    const bool c32 = ev[d.v] >= 65535;
+    const int64_t W = c32 ? kCycWindow / 2 : kCycWindow;
+    const int64_t K = ((int64_t)d.v + W - 1) / W;
+    const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(K, (d.E + share - 1) / share));
+    const int64_t kn = (K + parts - 1) / parts;
+    for (int64_t k0 = 0; k0 < K; k0 += kn)
+      tasks.push_back(CycTask{d.v, (int32_t)k0, (int32_t)std::min(kn, K - k0), c32 ? 1 : 0});
+    max_e = std::max(max_e, ev[d.v]);
   }
-  std::vector<int64_t> idx(roots.size());
-  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int64_t)i;
-  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
-  const double share = std::max(total / (double)(waves * 4), 1.0);
-  std::vector<int32_t> src, dst;
-  for (int64_t i : idx) {
-    int64_t parts = std::min<int64_t>(1024, std::max<int64_t>(1, (int64_t)std::ceil(work[i] / share)));
-    parts = std::min<int64_t>(parts, std::max<int64_t>(1, roots[i]));
-    for (int64_t q = 0; q < parts; ++q) {
-      src.push_back(roots[i]);
-      dst.push_back((int32_t)(q | (parts << 16)));
+  // heavy hash roots: id ranges of about `batch` wedges by degree mass
+  for (const auto& hr : ranged) {
+    const int32_t v = hr.second;
+    const int64_t P = (hr.first + batch - 1) / batch;
+    const int32_t r = (int32_t)roots.size();
+    roots.push_back(v);
+    int32_t x = 0;
+    for (int64_t i = 1; i <= P; ++i) {
+      int32_t y = v;
+      if (i < P) {
+        const int64_t target = (int64_t)((double)R.rp[v] * (double)i / (double)P);
+        y = (int32_t)(std::lower_bound(R.rp.begin(), R.rp.begin() + v, target) - R.rp.begin());
+        y = std::max(y, x);
+      }
+      if (y > x) tasks.push_back(CycTask{-(r + 1), r + 1, x, y});
+      x = y;
     }
   }
-  g.n_wedge = (int64_t)src.size();
-  st = dev_upload(c, &g.wedge_src, src.data(), src.size());
-  if (st) return st;
-  st = dev_upload(c, &g.wedge_dst, dst.data(), dst.size());
-  if (st) return st;
-  g.bytes += src.size() * 8;
-  g.wedge_key = waves;
+  // light roots packed into tasks; keys slot * n + w + 1 stay below 2^32
+  const int64_t max_slots = std::max<int64_t>(
+      1, std::min<int64_t>(1024, (int64_t)(UINT32_MAX / (uint64_t)std::max<int64_t>(n, 1))));
+  for (size_t i = 0; i < light.size();) {
+    const int32_t r0 = (int32_t)roots.size();
+    int64_t sum = 0;
+    while (i < light.size() && (int64_t)roots.size() - r0 < max_slots &&
+           (roots.size() == (size_t)r0 || sum + Ev[light[i]] <= batch)) {
+      sum += Ev[light[i]];
+      roots.push_back(light[i]);
+      ++i;
+    }
+    tasks.push_back(CycTask{-(r0 + 1), (int32_t)roots.size(), 0, INT32_MAX});
+  }
+  g.n_cyc = (int64_t)tasks.size();
+  g.cyc_max_e = max_e;
+  if (!tasks.empty()) {
+    st = dev_upload(c, &g.cyc_tasks, tasks.data(), tasks.size());
+    if (st) return st;
+  }
+  if (!roots.empty()) {
+    st = dev_upload(c, &g.cyc_roots, roots.data(), roots.size());
+    if (st) return st;
+  }
+  g.bytes += tasks.size() * sizeof(CycTask) + roots.size() * 4;
+  g.cyc_key = key;
   return GPM_OK;
 }
 
@@ -610,7 +702,6 @@ static int default_chunk(const gpm_ctx* c, int kind) {
   }
 }
 
-static int64_t kWedgeWaves(const gpm_ctx* c) { return (int64_t)c->cus * 8; }
 
 // Largest local graph of the workgroup kernel: one vertex per thread in its
 // scans, and its tile (plus the kernel's static LDS) within the workgroup's LDS.
@@ -895,19 +986,20 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
   }
 
   if (mode == GPM_EDGE_INDUCED && is_cycle4(p) && c->opt_cycle4_algo != 1) {
-    st = ensure_wedge(c, g, kWedgeWaves(c));
+    st = ensure_cycle(c, g);
     if (st) return st;
+    if (g.n_cyc == 0) { qw.has_constant = true; qw.constant = 0; return GPM_OK; }
     Job J{};
-    J.kind = kJobCycleWedge;
+    J.kind = kJobCycleBlock;
     J.k = 4;
     J.rp = g.ren.rp;
     J.col = g.ren.col;
-    J.task_src = g.wedge_src;
-    J.task_dst = g.wedge_dst;
-    J.n_tasks = g.n_wedge;
-    J.vertex_tasks = 1;
+    J.task_src = (const int32_t*)g.cyc_tasks;
+    J.task_dst = g.cyc_roots;
+    J.n_tasks = g.n_cyc;
     J.chunk = 1;
-    J.cap = (int32_t)n;  // counter words per wave
+    J.cap = g.cyc_max_e;  // cursor words per workgroup
+    J.n_vertices = (int32_t)n;
     js.jobs.push_back(J);
     js.need_words.push_back(0);
     qw.n_jobs += 1;
@@ -1155,7 +1247,7 @@ static void slot_free(Slot& s) {
   dev_free(s.d_meta);
   dev_free(s.d_res);
   dev_free(s.d_fbuf);
-  dev_free(s.d_zero);
+  dev_free(s.d_cursor);
   dev_free(s.d_tri);
   if (s.h_stage) (void)hipHostFree(s.h_stage);
   if (s.h_res) (void)hipHostFree(s.h_res);
@@ -1210,12 +1302,13 @@ static std::vector<LaunchPlan> plan_launches(JobPlanSet& js, std::vector<int>& p
   const int nj = (int)js.jobs.size();
   perm.resize(nj);
   for (int i = 0; i < nj; ++i) perm[i] = i;
-  // launches run in phases: workgroup jobs first (a kernel of their own), then
-  // the per-wave kinds, then the edge-term jobs, which read what the triangle
-  // scatter of the earlier phases left (kernel boundaries order them)
+  // launches run in phases: the workgroup kernels first (local-graph cliques,
+  // then 4-cycles, each a kernel of its own), then the per-wave kinds, then
+  // the edge-term jobs, which read what the triangle scatter of the earlier
+  // phases left (kernel boundaries order them)
   auto phase = [&](int i) {
     const int k = js.jobs[i].kind;
-    return k == kJobCliqueLgsBlock ? 0 : k == kJobEdgeTerms ? 2 : 1;
+    return k == kJobCliqueLgsBlock ? 0 : k == kJobCycleBlock ? 1 : k == kJobEdgeTerms ? 3 : 2;
   };
   std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
     if (phase(a) != phase(b)) return phase(a) < phase(b);
@@ -1363,24 +1456,19 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     if (s2 || waves < kWavesPerBlock)
       return fail(c, GPM_E_NOMEM, "frontier buffers do not fit the memory budget");
   }
-  // 4-cycle wedge jobs: one zero-initialised counter array per wave
+  // 4-cycle workgroup kernel: one cursor region per workgroup (the lower
+  // neighbours of the launch's largest direct root)
   int64_t zstride = 0;
+  bool any_cyc = false;
   for (int i = 0; i < nj; ++i)
-    if (jobs[i].kind == kJobCycleWedge) zstride = std::max<int64_t>(zstride, jobs[i].cap);
-  zstride = (int64_t)align_up((size_t)zstride, 64);
-  // plus the list of a task's distinct endpoints (a task with more falls back
-  // to a second walk over its wedges)
-  const int64_t zlist =
-      zstride ? (int64_t)align_up((size_t)std::min<int64_t>(zstride, c->opt_wedge_list), 64) : 0;
-  zstride += zlist;
-  if (zstride) {
-    waves = std::min<int64_t>(waves, kWedgeWaves(c));
-    const int64_t left = std::min<int64_t>((int64_t)frontier_budget - waves * stride * 4,
-                                           c->opt_wedge_mem);
-    const int64_t zw = left > 0 ? left / (zstride * 4) : 0;
-    if (zw < kWavesPerBlock) return fail(c, GPM_E_NOMEM, "wedge counters do not fit the memory budget");
-    waves = std::min(waves, zw);
-  }
+    if (jobs[i].kind == kJobCycleBlock) {
+      any_cyc = true;
+      zstride = std::max<int64_t>(zstride, jobs[i].cap);
+    }
+  zstride = any_cyc ? (int64_t)align_up((size_t)std::max<int64_t>(zstride, 1), 64) : 0;
+  int cyc_blocks = 0;
+  if (any_cyc && cycle_block_grid(c->cus, INT64_MAX, &cyc_blocks))
+    return fail(c, GPM_E_DEVICE, "4-cycle kernel occupancy query failed");
   waves = std::max<int64_t>(kWavesPerBlock, waves / kWavesPerBlock * kWavesPerBlock);
   const int blocks = (int)(waves / kWavesPerBlock);
   const size_t fbytes = (size_t)waves * (size_t)stride * 4;
@@ -1394,28 +1482,23 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
       fbuf = s.d_fbuf;
     }
   }
-  const size_t zbytes = (size_t)waves * (size_t)zstride * 4;
-  unsigned int* zbuf = nullptr;
-  if (zbytes && ar) {
-    if (fbytes + zbytes > frontier_budget)
-      return fail(c, GPM_E_NOMEM, "wedge counters exceed the allocation-free scratch");
-    zbuf = (unsigned int*)(ar->base + arena_fixed + fbytes);
-    if (launch_fill_u64((unsigned long long*)zbuf, (int64_t)(zbytes / 8), 0ull, s.stream))
-      return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
-  } else if (zbytes) {
-    // a reallocation may return the same address with new, uncleared memory
-    // beyond the old size: any change of capacity needs the fill
-    const size_t cap_before = s.d_zero_bytes;
-    st = grow_dev(c, (void**)&s.d_zero, &s.d_zero_bytes, zbytes);
-    if (st) return st;
-    if (s.d_zero_bytes != cap_before) s.zero_dirty = true;
-    if (s.zero_dirty) {
-      if (launch_fill_u64((unsigned long long*)s.d_zero, (int64_t)(s.d_zero_bytes / 8), 0ull,
-                          s.stream))
-        return fail(c, GPM_E_DEVICE, "fill kernel launch failed");
+  // cursor regions: fewer workgroups when they do not all fit the budget
+  if (any_cyc) {
+    const int64_t left = (int64_t)frontier_budget - (int64_t)fbytes;
+    const int64_t fit = left > 0 ? left / (zstride * 4) : 0;
+    if (fit < 1) return fail(c, GPM_E_NOMEM, "4-cycle cursor regions do not fit the memory budget");
+    cyc_blocks = (int)std::min<int64_t>(cyc_blocks, fit);
+  }
+  const size_t zbytes = (size_t)cyc_blocks * (size_t)zstride * 4;
+  int32_t* zbuf = nullptr;
+  if (zbytes) {
+    if (ar) {
+      zbuf = (int32_t*)(ar->base + arena_fixed + fbytes);
+    } else {
+      st = grow_dev(c, (void**)&s.d_cursor, &s.d_cursor_bytes, zbytes);
+      if (st) return st;
+      zbuf = s.d_cursor;
     }
-    s.zero_dirty = true;  // until this group completes (every task restores zeros)
-    zbuf = s.d_zero;
   }
   // per-edge triangle counters: one region per scatter group (its DAG edge
   // count, from the group's edge-term job), zero between launches
@@ -1529,14 +1612,16 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs | kKindTriScatter)) != 0;
     a.lds_words = uses_lds ? lds_words : 0;
     a.lgs_tile = lgs_T;
-    a.zbuf = (L.kinds & kKindCycleWedge) ? zbuf : nullptr;
+    a.zbuf = (L.kinds & kKindCycleBlock) ? zbuf : nullptr;
     a.zstride = zstride;
-    a.zlist = (int32_t)zlist;
     size_t lb = uses_lds ? lds_bytes : 0;
     int e;
     if (L.kinds == kKindCliqueLgsBlock) {
       a.lds_words = (int32_t)(blk_lds / 4);
       e = launch_lgs_block(c->opt_count_elements != 0, a, c->cus, L.chunks, blk_lds, s.stream);
+    } else if (L.kinds == kKindCycleBlock) {
+      e = launch_cycle_block(c->opt_count_elements != 0, a,
+                             (int)std::min<int64_t>(cyc_blocks, L.chunks), s.stream);
     } else {
       e = launch_persistent(L.kinds, c->opt_count_elements != 0, a, L.blocks, lb, s.stream);
     }
@@ -1568,7 +1653,6 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
 
 static gpm_status finish_sync(gpm_ctx* c, Slot& s) {
   HIP_TRY(c, hipStreamSynchronize(s.stream));
-  s.zero_dirty = false;
   s.tri_dirty = false;
   float ms = 0.f;
   if (s.n_launch > 0) HIP_TRY(c, hipEventElapsedTime(&ms, s.ev0, s.ev1));
@@ -1749,8 +1833,7 @@ static gpm_status progress(gpm_ctx* c) {
         finish_query(qw, s.h_out, r);
         complete(c, qw.ticket, GPM_OK, "", r);
       }
-      s.zero_dirty = false;
-      s.tri_dirty = false;
+          s.tri_dirty = false;
     }
     s.queries.clear();
     s.qkeys.clear();
@@ -2028,13 +2111,13 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "lgs_block") c->opt_lgs_block = v != 0;
   else if (k == "decompose") c->opt_decompose = v != 0;
   else if (k == "edge_terms") { if (v < 0 || v > 1) return fail(c, GPM_E_INVAL, "edge_terms 0..1"); c->opt_edge_terms = v; }
-  else if (k == "wedge_list") { if (v < 64 || v > (1 << 24)) return fail(c, GPM_E_INVAL, "wedge_list 64..2^24"); c->opt_wedge_list = v; }
+  else if (k == "cycle4_mode") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_mode 0..2"); c->opt_cycle4_mode = v; }
+  else if (k == "cycle4_batch") { if (v < 2 || v > (1 << 30)) return fail(c, GPM_E_INVAL, "cycle4_batch 2..2^30"); c->opt_cycle4_batch = v; }
   else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
   else if (k == "lgs_max") { if (v < 64 || v > kLgsMaxVertices) return fail(c, GPM_E_INVAL, "lgs_max 64..2048"); c->opt_lgs_max = v; }
   else if (k == "lgs_tile") { if (v < 64 || v > 256) return fail(c, GPM_E_INVAL, "lgs_tile 64..256"); c->opt_lgs_tile = v; }
   else if (k == "autotune") c->opt_autotune = v != 0;
-  else if (k == "wedge_mem") { if (v < (1 << 20)) return fail(c, GPM_E_INVAL, "wedge_mem >= 1 MiB"); c->opt_wedge_mem = v; }
   else if (k == "tune_min_ms") { if (v < 0) return fail(c, GPM_E_INVAL, "tune_min_ms >= 0"); c->opt_tune_min_ms = v; }
   else if (k == "max_batch") { if (v < 1) return fail(c, GPM_E_INVAL, "max_batch >= 1"); c->opt_max_batch = v; }
   else if (k == "serve_slots") { if (v < 1 || v > kMaxSlots) return fail(c, GPM_E_INVAL, "serve_slots 1..4"); c->opt_serve_slots = v; }
@@ -2114,7 +2197,7 @@ gpm_status gpm_prepare(gpm_ctx* c, int32_t id) {
   if (st) return st;
   st = ensure_lower(c, *g);
   if (st) return st;
-  return ensure_wedge(c, *g, kWedgeWaves(c));
+  return ensure_cycle(c, *g);
 }
 
 gpm_status gpm_graph_info(gpm_ctx* c, int32_t id, gpm_graph_meta* out) {

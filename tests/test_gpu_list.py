@@ -243,6 +243,29 @@ def has_edges(g, u, v):
     return out
 
 
+def rows_are_cliques_on_device(g, rows, chunk=1 << 25):
+    """Every row of `rows` (a [R, k] device tensor) a k-clique of g: every pair
+    of its vertices adjacent, looked up on the device in the sorted key array
+    src * n + col of the CSR (one batched binary search per pair)."""
+    import torch
+    n = g.n
+    rp = torch.from_numpy(np.asarray(g.row_ptr, dtype=np.int64)).cuda()
+    src = torch.repeat_interleave(torch.arange(n, device="cuda", dtype=torch.int64),
+                                  rp[1:] - rp[:-1])
+    keys = src * n + torch.from_numpy(np.asarray(g.col, dtype=np.int64)).cuda()
+    del src
+    assert bool((keys[1:] > keys[:-1]).all())
+    k = rows.shape[1]
+    for lo in range(0, rows.shape[0], chunk):
+        part = rows[lo:lo + chunk].to(torch.int64)
+        for a, b in itertools.combinations(range(k), 2):
+            q = part[:, a] * n + part[:, b]
+            idx = torch.searchsorted(keys, q).clamp_(max=keys.numel() - 1)
+            if not bool((keys[idx] == q).all()):
+                return False
+    return True
+
+
 def test_list_rmat_cliques_by_properties(ctx, oracle):
     import torch
     g = synth.rmat(12, 8, seed=361)
@@ -256,11 +279,12 @@ def test_list_rmat_cliques_by_properties(ctx, oracle):
             rows = np.sort(buf.cpu().numpy().astype(np.int64), axis=1)
             # distinct vertex sets
             assert len(np.unique(rows, axis=0)) == cnt
-            # every pair adjacent (and so every row a k-clique); a sample of rows
-            rng = np.random.default_rng(5)
-            pick = rng.choice(cnt, size=min(cnt, 4000), replace=False)
-            for a, b in itertools.combinations(range(k), 2):
-                assert has_edges(g, rows[pick, a], rows[pick, b]).all()
+            # every pair of every row adjacent (so every row a k-clique)
+            assert rows_are_cliques_on_device(g, buf)
+            # the device check itself finds a row that is not a clique
+            bad = buf[:2].clone()
+            bad[1, 1] = bad[1, 0]
+            assert not rows_are_cliques_on_device(g, bad)
     finally:
         ctx.unload(gid)
 
@@ -304,8 +328,9 @@ def test_list_full_size_workload(ctx):
     """The listing workload at full size (R-MAT scale 16, edge factor 16:
     293M 4-cliques, 4.7 GB of rows), in the launch bench.py times: the count
     equals the stored oracle value, every row has 4 distinct vertices, no two
-    rows share a vertex set (all rows, sorted on the device), and sampled rows
-    are 4-cliques."""
+    rows share a vertex set (all rows, sorted on the device), and every row is
+    a 4-clique (all six pairs of every row looked up on the device) -- which
+    together make the rows exactly the set of 4-cliques."""
     import json
     import os
     import torch
@@ -329,8 +354,10 @@ def test_list_full_size_workload(ctx):
         key = torch.sort(key).values
         assert bool((key[1:] != key[:-1]).all()), "a 4-clique listed twice"
         del key
+        assert rows_are_cliques_on_device(g, rows)
+        # spot check of the device lookup against the host one
         rng = np.random.default_rng(13)
-        pick = torch.from_numpy(rng.choice(cnt, size=5000, replace=False)).cuda()
+        pick = torch.from_numpy(rng.choice(cnt, size=2000, replace=False)).cuda()
         sample = rows[pick].cpu().numpy().astype(np.int64)
         for a, b in itertools.combinations(range(4), 2):
             assert has_edges(g, sample[:, a], sample[:, b]).all()

@@ -183,7 +183,8 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                           ("lgs_tile", [64, 256]), ("lgs_max", [64, 100]),
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
                           ("rename", [0]), ("cycle4_algo", [1, 2]), ("decompose", [0]),
-                          ("edge_terms", [1])]:
+                          ("edge_terms", [1]), ("cycle4_mode", [1, 2]),
+                          ("cycle4_batch", [16, 1 << 20])]:
             for v in vals:
                 ctx.set_option(opt, v)
                 for n, e in exp.items():
@@ -193,7 +194,8 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                                  "clique_lds": 1, "granularity": 0, "clique_algo": 0,
                                  "lgs_tile": 128, "lgs_max": 2048, "lgs_split": 1,
                                  "leaf_cap": 128, "rename": 1, "cycle4_algo": 0,
-                                 "decompose": 1, "edge_terms": 0}[opt])
+                                 "decompose": 1, "edge_terms": 0, "cycle4_mode": 0,
+                                 "cycle4_batch": 8192}[opt])
     finally:
         ctx.unload(gid)
 
@@ -358,25 +360,39 @@ def test_workgroup_unordered_dag(ctx):
         ctx.unload(did)
 
 
-def test_wedge_counters_across_layouts(ctx, oracle):
-    """4-cycle counter arrays are laid out per launch by the largest graph's
-    vertex count; interleaving graphs of different sizes (and motif queries
-    that share the launch with other kinds) must never see a stale counter or
-    list entry, with the distinct-endpoint list large or overflowing."""
+def test_cycle4_task_kinds(ctx, oracle):
+    """Edge-induced 4-cycles by the workgroup kernel's three kinds of task --
+    direct id windows (16- and 32-bit counters), hash tasks over id ranges of
+    one root, packed light roots -- and its split of a hash task whose
+    distinct endpoints overflow the table: every mode and task size gives the
+    closed forms and the oracle, interleaved with other graphs and with motif
+    queries that share the launch."""
+    import math
     gs = [synth.rmat(12, 8, seed=1401), synth.grid(5, 7), synth.complete(9),
-          synth.rmat(10, 8, seed=1402), synth.chung_lu(3000, 8.0, 2.1, 300.0, 12000, 1403)]
-    ids = [ctx.load(g) for g in gs]
+          synth.rmat(14, 16, seed=1402), synth.chung_lu(30000, 8.0, 2.1, 3000.0, 120000, 1403),
+          synth.complete_bipartite(2, 70000),    # a root with 70000 lower neighbours
+          synth.complete_bipartite(3, 40000),    # 16-bit window counters up to 39999
+          synth.hypercube(10)]
     exp_c4 = [oracle.cycle4(g) for g in gs]
-    exp_m4 = [oracle.motifs4(g) for g in gs]
+    assert exp_c4[5] == math.comb(70000, 2)
+    assert exp_c4[6] == 3 * math.comb(40000, 2)
+    assert exp_c4[7] == math.comb(10, 2) * 2 ** 8
+    exp_m4 = {i: oracle.motifs4(gs[i]) for i in (0, 1, 2, 3, 4)}
+    ids = [ctx.load(g) for g in gs]
     try:
-        for cap in (64, 1 << 19, 64):
-            ctx.set_option("wedge_list", cap)
+        for mode, batch in ((0, 8192), (1, 8192), (2, 8192), (1, 16), (2, 64), (0, 1 << 20),
+                            (1, 1 << 20)):
+            ctx.set_option("cycle4_mode", mode)
+            ctx.set_option("cycle4_batch", batch)
             for rep in range(2):
-                for i in ([0, 1, 2, 3, 4] if rep == 0 else [4, 2, 0, 3, 1]):
-                    assert ctx.count(ids[i], "cycle4", E) == exp_c4[i], (cap, i)
-                    assert ctx.motifs(ids[i], 4) == exp_m4[i], (cap, i)
+                order = range(len(gs)) if rep == 0 else reversed(range(len(gs)))
+                for i in order:
+                    assert ctx.count(ids[i], "cycle4", E) == exp_c4[i], (mode, batch, i)
+                    if i in exp_m4 and rep == 0:
+                        assert ctx.motifs(ids[i], 4) == exp_m4[i], (mode, batch, i)
     finally:
-        ctx.set_option("wedge_list", 1 << 19)
+        ctx.set_option("cycle4_mode", 0)
+        ctx.set_option("cycle4_batch", 8192)
         for gid in ids:
             ctx.unload(gid)
 
