@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--workload", default="clique",
                     choices=["clique", "triangle", "chunglu", "batch", "serve", "list"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--queries", default="cycle4,diamond,tailed_triangle,motifs3",
+                    help="chunglu workload: the queries to time (comma separated)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default kernel knobs (fixed dispatch sequence)")
     ap.add_argument("--option", action="append", default=[],
@@ -92,6 +94,44 @@ def measured_traffic(k, kinds):
 LIST_TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856ae6169957da11ce16fb",
                 "fetch_kib": 160388.1, "write_kib": 5050520.3,
                 "fetch_factor": 2.0, "write_factor": 1.0}
+
+
+# gpm_cycle_block (4-cycles) on the Chung-Lu workload: the same two counter
+# passes (KiB per dispatch), valid for the sources they were taken on
+CYC_TRAFFIC = {"sources_sha256": "", "fetch_kib": 0.0, "write_kib": 0.0,
+               "fetch_factor": 2.0, "write_factor": 1.0}
+
+
+def measured_cycle_traffic():
+    if not CYC_TRAFFIC["sources_sha256"] or CYC_TRAFFIC["sources_sha256"] != sources_sha256():
+        return None
+    return 1024.0 * (CYC_TRAFFIC["fetch_kib"] * CYC_TRAFFIC["fetch_factor"] +
+                     CYC_TRAFFIC["write_kib"] * CYC_TRAFFIC["write_factor"])
+
+
+def cpu_baseline_chunglu(g, names):
+    """The oracle's routes for the same queries on the same graph, timed on
+    the host's cores: codegree 4-cycles, the local 4-vertex terms (diamond,
+    tailed triangle), the induced 3-motifs."""
+    from oracle import pyoracle
+    progress("CPU oracle baseline (Chung-Lu queries)")
+    routes = {"cycle4": lambda: pyoracle.cycle4(g),
+              "diamond": lambda: pyoracle.nonind4_local(g, 1)[3],
+              "tailed_triangle": lambda: pyoracle.nonind4_local(g, 1)[2],
+              "motifs3": lambda: pyoracle.motifs3(g, 1)}
+    per, total = {}, 0.0
+    counts = {}
+    for name in names:
+        t = time.perf_counter()
+        counts[name] = routes[name]()
+        dt = (time.perf_counter() - t) * 1e3
+        per[name] = dt
+        total += dt
+    out = {"value": total, "unit": "ms", "cores": pyoracle.num_threads(), "kind": "oracle",
+           "sample": "the full graph, the same queries, each by the oracle's own route "
+                     "(sum of one run each)", "ms_by_query": per}
+    out.update(host_cpu())
+    return out, counts
 
 
 def measured_list_traffic():
@@ -386,7 +426,8 @@ def run_chunglu(args, ctx, torch):
         ctx.set_option("autotune", 1)
     res = {}
     total = 0.0
-    for name in ("cycle4", "diamond", "tailed_triangle", "motifs3"):
+    names = [q for q in args.queries.split(",") if q]
+    for name in names:
         def call():
             return ctx.motifs(gid, 3) if name == "motifs3" else ctx.count(gid, name, 1)
         for _ in range(max(args.warmup, 1)):
@@ -403,15 +444,37 @@ def run_chunglu(args, ctx, torch):
         res[name] = {"median_ms": med, "kernel_ms_median": statistics.median(kms), "count": c,
                      "parity_vs_stored_oracle": (c == expect[name]) if ok else None}
         progress(f"{name}: {med:.1f} ms")
-    return {"metric": "count time, Chung-Lu n=4M m=60M (sum of the medians of 4 queries)",
-            "value": total, "unit": "ms", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": total, "higher_is_better": False,
-            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-            "config": {"workload": "chung_lu_4m_gamma2.1", "n": g.n, "m": g.m,
-                       "max_degree": info["max_degree"],
-                       "queries": ["cycle4 (edge-induced)", "diamond (edge-induced)",
-                                   "tailed_triangle (edge-induced)", "motifs(3)"]},
-            "prepare_s": prepare_s, "queries": res}
+    out = {"metric": f"count time, Chung-Lu n=4M m=60M (sum of the medians of {len(names)} "
+                     f"queries)",
+           "value": total, "unit": "ms", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": total, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "chung_lu_4m_gamma2.1", "n": g.n, "m": g.m,
+                      "max_degree": info["max_degree"], "queries": names},
+           "prepare_s": prepare_s, "queries": res}
+    if "cycle4" in names:
+        # roofline of the 4-cycle launch (the step's longest): algorithmic
+        # bytes = 4 B per wedge endpoint read + 16 B per neighbour-list visit
+        # (offsets), from an instrumented pass (never timed)
+        ctx.set_option("count_elements", 1)
+        ctx.count(gid, "cycle4", 1)
+        si = ctx.stats()
+        ctx.set_option("count_elements", 0)
+        ms = res["cycle4"]["kernel_ms_median"]
+        byts = 4 * si["elements"] + 16 * si["list_fetches"]
+        gbs = byts / (ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "gpm_cycle_block (4-cycle wedge aggregation "
+                                                     "in LDS, one workgroup per task)",
+                           "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": measured_cycle_traffic(),
+                           "algorithmic_bytes_per_launch": byts, "launch_ms": ms,
+                           "wedges_per_launch": si["elements"],
+                           "list_visits_per_launch": si["list_fetches"],
+                           "wedges_per_s": si["elements"] / (ms * 1e-3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], oc = cpu_baseline_chunglu(g, names)
+        out["cpu_baseline_counts_match"] = all(oc[q] == res[q]["count"] for q in names)
+    return out
 
 
 def _gen_batch(i):

@@ -85,23 +85,30 @@ constexpr int kSortWords = kSortBatch + 64;
 constexpr int kBlockSortWords = kBlockWaves * kSortWords;
 
 // 4-cycle workgroup kernel (kJobCycleBlock): 1024 threads, a table of
-// kCycTableWords words of LDS.  Direct windows count the endpoints of one id
-// window in 16-bit counters packed two per word (kCycWindow ids), or in
-// 32-bit counters (half the ids) for roots with 65535 or more lower
-// neighbours.  Hash tasks use the table as keys | counts (kCycSlots each);
-// a task stops and splits once kCycHashCap distinct keys are in.
+// kCycTableWords words of LDS (one workgroup per CU).  Direct windows
+// count the endpoints of one id window in 16-bit counters packed two per
+// word (kCycWindow ids), or in 32-bit counters (half the ids) for roots with
+// 65535 or more lower neighbours.  Hash tasks use the table as keys | counts
+// (kCycSlots each); a task stops and splits once kCycHashCap distinct keys
+// are in.
 constexpr int kCycWaves = 16;
-constexpr int kCycTableWords = 32768;
+constexpr int kCycSlotBits = 14;
+constexpr int kCycSlots = 1 << kCycSlotBits;
+constexpr int kCycTableWords = 2 * kCycSlots;
 constexpr int kCycWindow = 2 * kCycTableWords;
-constexpr int kCycSlots = kCycTableWords / 2;
 constexpr int kCycHashCap = kCycSlots * 3 / 4;
 constexpr int kCycStack = 64;   // pending split tasks per workgroup
 
-// A task of the 4-cycle kernel, 4 int32 words.  head >= 0: direct windows of
-// root v = head: windows a .. a+b-1 (window i covers ids [i*W, (i+1)*W) below
-// v; W = kCycWindow, or kCycWindow / 2 when c & 1: 32-bit counters).
-// head < 0: hash task over the roots r[-head-1 .. a) of the job's root list
-// (task_dst) with endpoints in [b, c) (and below each root).
+// A task of the 4-cycle kernel, 4 int32 words.
+//  head >= 0, c & kCycRanges == 0: direct windows of root v = head: windows
+//    a .. a+b-1 (window i covers ids [i*W, (i+1)*W) below v; W = kCycWindow,
+//    or kCycWindow / 2 when c & kCycWide: 32-bit counters);
+//  head >= 0, c & kCycRanges: hash ranges of root v = head: ranges a .. a+b-1
+//    of the job's boundary list (range i covers ids [bd[i], bd[i + 1]));
+//  head < 0: hash task over the roots r[-head-1 .. a) of the job's root list
+//    (task_dst) with endpoints in [b, c) (and below each root).
+constexpr int32_t kCycWide = 1;
+constexpr int32_t kCycRanges = 2;
 struct CycTask {
   int32_t head;
   int32_t a;
@@ -138,6 +145,7 @@ struct Job {
   const int64_t* deg_rp;   // kJobEdgeTerms: offsets of the symmetric graph (degrees)
   int32_t n_vertices;      // kJobCycleBlock: vertices of the graph (hash keys)
   int32_t pad_;
+  const int32_t* bounds;   // kJobCycleBlock: id boundaries of the hash ranges
 };
 
 struct KernelArgs {

@@ -1761,17 +1761,19 @@ gpm_lgs_block(KernelArgs a) {
 // counts the wedges of one task in a table in its LDS:
 //  - direct windows (roots whose endpoints are dense among the ids below
 //    them): one counter per endpoint id of a window; each lane keeps its
-//    position in N(u) (its cursor, in the workgroup's HBM region) from one
-//    window of the task to the next, so a window costs one search per u;
-//  - hash tasks (light roots batched, or an id range of one root): keys
-//    slot * n + w + 1 with their counts; a task that meets more distinct keys
-//    than kCycHashCap stops, splits (its roots in halves, else its id range
-//    in halves) and runs again.
+//    u's list position and end (its cursor, in the workgroup's HBM region)
+//    from one window of the task to the next, so a window costs one
+//    coalesced cursor read and a short search from the cursor per u;
+//  - hash ranges (other roots with many wedges): keys w + 1 with their
+//    counts, the root's id ranges in order with cursors as above; a range
+//    that meets more distinct keys than kCycHashCap runs again in halves;
+//  - hash batches (light roots): keys slot * n + w + 1; a batch that meets
+//    more distinct keys than kCycHashCap splits its roots in halves and runs
+//    again.
 // Every phase leaves the table at zero.
 // ---------------------------------------------------------------------------
 
-static_assert(kCycSlots == (1 << 14), "hash of the 4-cycle table assumes 2^14 slots");
-static_assert(kCycWindow == 65536, "16-bit window counters assume 65536 ids");
+static_assert(kCycHashCap + kCycWaves * 64 < kCycSlots, "a 4-cycle hash table must never fill");
 
 struct CycShared {
   int64_t S[kCycWaves][64];     // per wave: list start of each lane's slice
@@ -1784,12 +1786,33 @@ struct CycShared {
 };
 
 __device__ __forceinline__ uint32_t cyc_hash(uint32_t key) {
-  return (key * 2654435761u) >> 18;
+  return (key * 2654435761u) >> (32 - kCycSlotBits);
+}
+
+// First index i in [lo, n) with a[i] >= key, given a[lo - 1] < key (or lo =
+// 0): one probe when a[lo] >= key already, else an exponential search from
+// lo (the probes stay near lo, where the previous window's slice ended).
+__device__ __forceinline__ int32_t gallop_lb(const int32_t* __restrict__ a, int32_t lo,
+                                             int32_t n, int32_t key) {
+  if (lo >= n || a[lo] >= key) return lo;
+  int32_t base = lo;  // a[base] < key
+  int32_t step = 1;
+  while (base + step < n && a[base + step] < key) {
+    base += step;
+    step <<= 1;
+  }
+  const int32_t hi = min(base + step, n);  // a[hi] >= key, or hi == n
+  return base + 1 + lower_bound(a + base + 1, hi - base - 1, key);
 }
 
 // One batch of up to 64 slices per wave: lane l holds the slice
-// col[start, start + len); the wave takes the slices' elements 64 at a time
-// (each lane finds its slice in the staged prefix) and hands each to sink.
+// col[start, start + len); the wave takes the slices' elements 64 * kCycEpl at
+// a time, kCycEpl consecutive ones per lane: one search of the staged prefix
+// finds the slice of a lane's first element, the next ones follow by
+// stepping to the next slice when one ends, and their loads are in flight
+// together (the kernel is latency-bound; its LDS table allows one workgroup
+// per CU, which leaves registers for them); each element goes to sink.
+constexpr int kCycEpl = 4;
 template <bool CE, typename Sink>
 __device__ __forceinline__ void cyc_batch(const int32_t* __restrict__ col, int64_t start,
                                           int32_t len, int64_t* S, int32_t* PF,
@@ -1800,26 +1823,49 @@ __device__ __forceinline__ void cyc_batch(const int32_t* __restrict__ col, int64
   PF[l] = incl;
   wave_sync_mem();
   const int32_t tot = uni(__shfl(incl, 63, 64));
-  for (int32_t tb = 0; tb < tot; tb += 64) {
-    const int32_t t = tb + l;
-    if (t < tot) {
-      const int32_t o = upper_bound(PF, 64, t);
-      const int32_t r = t - (o > 0 ? PF[o - 1] : 0);
-      sink(col[S[o] + r]);
+  for (int32_t tb = 0; tb < tot; tb += 64 * kCycEpl) {
+    const int32_t t0 = tb + kCycEpl * l;
+    int32_t w[kCycEpl];
+#pragma unroll
+    for (int j = 0; j < kCycEpl; ++j) w[j] = 0;
+    if (t0 < tot) {
+      // element t of slice o lies at col[S[o] + t - PF[o - 1]]
+      int32_t o = upper_bound(PF, 64, t0);
+      int32_t end = PF[o];
+      int64_t base = S[o] - (o > 0 ? PF[o - 1] : 0);
+#pragma unroll
+      for (int j = 0; j < kCycEpl; ++j) {
+        const int32_t t = t0 + j;
+        if (t < tot) {
+          while (t >= end) {  // t < tot = PF[63]: some later slice holds it
+            ++o;
+            base = S[o] - end;
+            end = PF[o];
+          }
+          w[j] = col[base + t];
+        }
+      }
     }
+#pragma unroll
+    for (int j = 0; j < kCycEpl; ++j)
+      if (t0 + j < tot) sink(w[j]);
   }
   if (CE) ec.elems += (uint64_t)tot;
   wave_sync_mem();
 }
 
-// Direct windows a .. a+b-1 of root v (see CycTask).
+// Direct windows a .. a+b-1 of root v (see CycTask).  cursor: two int64
+// per lower neighbour: the list position, and the number of list elements
+// left with the value of the next one (INT32_MAX past the end) packed as
+// rem | next << 32, so that a window the list does not reach is skipped
+// without touching the list.
 template <bool CE>
 __device__ __forceinline__ void cyc_direct(const int64_t* __restrict__ rp,
                                            const int32_t* __restrict__ col, const CycTask& T,
-                                           uint32_t* tab, int32_t* cursor, CycShared& sh,
+                                           uint32_t* tab, int64_t* cursor, CycShared& sh,
                                            uint64_t& acc, ElemCounter& ec) {
   const int32_t v = T.head;
-  const bool c32 = (T.c & 1) != 0;
+  const bool c32 = (T.c & kCycWide) != 0;
   const int64_t W = c32 ? kCycWindow / 2 : kCycWindow;
   const int32_t* Nv = col + rp[v];
   const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
@@ -1835,14 +1881,36 @@ __device__ __forceinline__ void cyc_direct(const int64_t* __restrict__ rp,
       int64_t start = 0;
       int32_t len = 0;
       if (i < e) {
-        const int32_t u = Nv[i];
-        const int64_t s0 = rp[u];
-        const int32_t du = (int32_t)(rp[u + 1] - s0);
-        const int32_t lo = (k == T.a) ? lower_bound(col + s0, du, wa) : cursor[i];
-        const int32_t hi = lo + lower_bound(col + s0 + lo, du - lo, wb);
-        cursor[i] = hi;
-        start = s0 + lo;
-        len = hi - lo;
+        // the slice of N(u) in [wa, wb): from the cursor the previous window
+        // left (a search at the task's first window), up to wb by galloping
+        int64_t pos;
+        int32_t rem, nxt;
+        const bool first = k == T.a;
+        if (first) {
+          const int32_t u = Nv[i];
+          pos = rp[u];
+          const int64_t end = rp[u + 1];
+          if (wa > 0) pos += lower_bound(col + pos, (int32_t)(end - pos), wa);
+          rem = (int32_t)(end - pos);
+          nxt = rem > 0 ? col[pos] : INT32_MAX;
+        } else {
+          pos = cursor[2 * i];
+          const int64_t pk = cursor[2 * i + 1];
+          rem = (int32_t)(uint32_t)pk;
+          nxt = (int32_t)(pk >> 32);
+        }
+        if (nxt < wb)  // col[pos] = nxt is in the window
+          len = 1 + gallop_lb(col + pos + 1, 0, rem - 1, wb);
+        start = pos;
+        if (len > 0) {
+          pos += len;
+          rem -= len;
+          nxt = rem > 0 ? col[pos] : INT32_MAX;
+        }
+        if (first || len > 0) {
+          cursor[2 * i] = pos;
+          cursor[2 * i + 1] = (int64_t)(uint32_t)rem | ((int64_t)nxt << 32);
+        }
       }
       if (CE) ec.fetches += (uint64_t)min(64, e - ub);
       if (c32) {
@@ -1871,6 +1939,120 @@ __device__ __forceinline__ void cyc_direct(const int64_t* __restrict__ rp,
       }
     }
     __syncthreads();
+  }
+}
+
+// Hash ranges a .. a+b-1 of root v (see CycTask): the ranges in order, each
+// lane's list position carried from one range to the next in the cursor; a
+// range whose distinct endpoints overflow the table runs again as two halves
+// from the same positions.  cursor: three int64 per lower neighbour (list
+// position, list end, position after the running range).
+template <bool CE>
+__device__ __forceinline__ void cyc_ranges(const int64_t* __restrict__ rp,
+                                           const int32_t* __restrict__ col,
+                                           const int32_t* __restrict__ bounds,
+                                           const CycTask& T, uint32_t* tab, int64_t* cursor,
+                                           CycShared& sh, uint64_t& acc, ElemCounter& ec) {
+  uint32_t* keys = tab;
+  uint32_t* cnts = tab + kCycSlots;
+  const int32_t v = T.head;
+  const int32_t* Nv = col + rp[v];
+  const int32_t e = uni(lower_bound(Nv, (int32_t)(rp[v + 1] - rp[v]), v));
+  const int wv = (int)(threadIdx.x >> 6);
+  const int l = lane_id();
+  const int32_t x0 = uni(bounds[T.a]);
+  // cursors at the first range's start (thread i*1024 + t keeps lower
+  // neighbour i*1024 + t, as in the walk below)
+  for (int32_t i = (int32_t)threadIdx.x; i < e; i += kCycWaves * 64) {
+    const int32_t u = Nv[i];
+    int64_t pos = rp[u];
+    const int64_t end = rp[u + 1];
+    if (x0 > 0) pos += lower_bound(col + pos, (int32_t)(end - pos), x0);
+    cursor[3 * i] = pos;
+    cursor[3 * i + 1] = end;
+  }
+  for (int32_t r = 0; r < T.b; ++r) {
+    if (threadIdx.x == 0) {
+      sh.stack[0][2] = bounds[T.a + r];
+      sh.stack[0][3] = bounds[T.a + r + 1];
+      sh.sp = 1;
+    }
+    __syncthreads();
+    for (;;) {
+      const int32_t sp = uni(sh.sp);
+      if (sp == 0) break;
+      const int32_t x = uni(sh.stack[sp - 1][2]);
+      const int32_t y = uni(sh.stack[sp - 1][3]);
+      __syncthreads();  // every wave has read the entry before it is popped
+      if (threadIdx.x == 0) {
+        sh.sp = sp - 1;
+        sh.distinct = 0;
+        sh.overflow = 0;
+      }
+      __syncthreads();
+      for (int32_t ub = wv * 64; ub < e; ub += kCycWaves * 64) {
+        if (uni(__hip_atomic_load(&sh.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)))
+          break;
+        const int32_t i = ub + l;
+        int64_t start = 0;
+        int32_t len = 0;
+        if (i < e) {
+          const int64_t pos = cursor[3 * i];
+          const int64_t end = cursor[3 * i + 1];
+          len = gallop_lb(col + pos, 0, (int32_t)(end - pos), y);
+          start = pos;
+          cursor[3 * i + 2] = pos + len;
+        }
+        if (CE) ec.fetches += (uint64_t)min(64, e - ub);
+        cyc_batch<CE>(col, start, len, sh.S[wv], sh.PF[wv], ec, [&](int32_t w) {
+          if (__hip_atomic_load(&sh.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+          const uint32_t key = (uint32_t)w + 1u;
+          uint32_t h = cyc_hash(key);
+          for (;;) {
+            const uint32_t old = atomicCAS(&keys[h], 0u, key);
+            if (old == 0u) {
+              if (atomicAdd(&sh.distinct, 1u) + 1u > (uint32_t)kCycHashCap)
+                __hip_atomic_store(&sh.overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              atomicAdd(&cnts[h], 1u);
+              break;
+            }
+            if (old == key) {
+              atomicAdd(&cnts[h], 1u);
+              break;
+            }
+            h = (h + 1u) & (uint32_t)(kCycSlots - 1);
+          }
+        });
+      }
+      __syncthreads();
+      if (uni(sh.overflow)) {
+        // the halves run next, from the same positions (a range of at most
+        // kCycHashCap ids cannot overflow, so the halving ends)
+        for (int32_t q = (int32_t)threadIdx.x; q < kCycTableWords; q += kCycWaves * 64) tab[q] = 0;
+        if (threadIdx.x == 0) {
+          const int32_t mid = x + (y - x) / 2;
+          int32_t t = sh.sp;
+          sh.stack[t][2] = mid; sh.stack[t][3] = y; ++t;
+          sh.stack[t][2] = x; sh.stack[t][3] = mid; ++t;
+          sh.sp = t;
+        }
+        __syncthreads();
+        continue;
+      }
+      for (int32_t q = (int32_t)threadIdx.x; q < kCycSlots; q += kCycWaves * 64) {
+        if (keys[q]) {
+          const uint64_t c = cnts[q];
+          acc += c * (c - 1) / 2;
+          keys[q] = 0;
+          cnts[q] = 0;
+        }
+      }
+      // the range is done: its end positions become the cursors
+      for (int32_t i = (int32_t)threadIdx.x; i < e; i += kCycWaves * 64)
+        cursor[3 * i] = cursor[3 * i + 2];
+      __syncthreads();
+    }
   }
 }
 
@@ -1926,8 +2108,8 @@ __device__ __forceinline__ void cyc_hash_task(const int64_t* __restrict__ rp,
           const int32_t u = Nv[i];
           const int64_t s0 = rp[u];
           const int32_t du = (int32_t)(rp[u + 1] - s0);
-          const int32_t lo = lower_bound(col + s0, du, x);
-          len = lower_bound(col + s0 + lo, du - lo, hy);
+          const int32_t lo = x == 0 ? 0 : lower_bound(col + s0, du, x);
+          len = gallop_lb(col + s0, lo, du, hy) - lo;
           start = s0 + lo;
         }
         if (CE) ec.fetches += (uint64_t)min(64, e - ub);
@@ -2001,7 +2183,7 @@ gpm_cycle_block(KernelArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t cyc_tab[];
   __shared__ CycShared sh;
   for (int32_t q = (int32_t)threadIdx.x; q < kCycTableWords; q += kCycWaves * 64) cyc_tab[q] = 0;
-  int32_t* cursor = a.zbuf + (int64_t)blockIdx.x * a.zstride;
+  int64_t* cursor = (int64_t*)(a.zbuf + (int64_t)blockIdx.x * a.zstride);
   const int home = (int)(blockIdx.x & (kQueues - 1));
   uint32_t dead = 0;
   int cur = -1;
@@ -2033,7 +2215,9 @@ gpm_cycle_block(KernelArgs a) {
       T.a = uni(tasks[t].a);
       T.b = uni(tasks[t].b);
       T.c = uni(tasks[t].c);
-      if (T.head >= 0)
+      if (T.head >= 0 && (T.c & kCycRanges))
+        cyc_ranges<CE>(J.rp, J.col, J.bounds, T, cyc_tab, cursor, sh, acc[0], ec);
+      else if (T.head >= 0)
         cyc_direct<CE>(J.rp, J.col, T, cyc_tab, cursor, sh, acc[0], ec);
       else
         cyc_hash_task<CE>(J.rp, J.col, J.task_dst, (uint32_t)J.n_vertices, T, cyc_tab, sh,

@@ -82,8 +82,9 @@ struct Graph {
   // records) and the root list of its hash tasks
   CycTask* cyc_tasks = nullptr;
   int32_t* cyc_roots = nullptr;
+  int32_t* cyc_bounds = nullptr;  // id boundaries of the hash ranges
   int64_t n_cyc = 0;
-  int32_t cyc_max_e = 0;          // lower neighbours of the largest direct root (cursor words)
+  int32_t cyc_max_e = 0;          // cursor words per workgroup
   int64_t cyc_key = -1;
   int32_t* lo_src = nullptr;  // root edges (v0, v1) with v1 < v0 (lazy)
   int32_t* lo_dst = nullptr;
@@ -176,7 +177,8 @@ struct gpm_ctx {
   int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
   int64_t opt_decompose = 1;                    // counting-only decomposition of named motifs
   int64_t opt_cycle4_mode = 0;                  // 0 cost model, 1 hash tasks only, 2 direct windows
-  int64_t opt_cycle4_batch = 8192;              // wedges per 4-cycle hash task
+  int64_t opt_cycle4_batch = kCycHashCap * 2 / 3;  // wedges per 4-cycle hash task
+  int64_t opt_cycle4_split = 4;                 // direct parts per workgroup (load balance)
   int64_t opt_edge_terms = 0;                   // 0 auto (triangle scatter), 1 per-edge intersection
   int lds_block_max = 65536;                    // dynamic LDS per workgroup (bytes)
   int64_t opt_tune_min_ms = 20;
@@ -259,8 +261,10 @@ static void free_graph(Graph& g) {
   g.ren_ids = nullptr;
   dev_free(g.cyc_tasks);
   dev_free(g.cyc_roots);
+  dev_free(g.cyc_bounds);
   g.cyc_tasks = nullptr;
   g.cyc_roots = nullptr;
+  g.cyc_bounds = nullptr;
   dev_free(g.ren_lo_src);
   dev_free(g.ren_lo_dst);
   g.ren_lo_src = g.ren_lo_dst = nullptr;
@@ -532,24 +536,26 @@ static gpm_status ensure_ren(gpm_ctx* c, Graph& g) {
 // Tasks of the 4-cycle workgroup kernel on the relabelled graph.  Root v
 // (the cycle's largest vertex) has e_v lower neighbours u and
 // E_v = sum_u |N(u) ∩ [0, v)| wedges; roots with fewer than two wedges hold no
-// 4-cycle.  A root goes to direct windows when counting every id below it
-// (v/2 counter words, 2 searches per u and window, one increment per wedge)
-// costs less than hashing its wedges (about 4 table operations per wedge);
-// direct roots are cut into parts of consecutive windows of about equal
-// share.  Other roots with more than `batch` wedges become hash tasks over id
-// ranges of about `batch` wedges each (the ranges follow the degree mass
-// rp[x], since a wedge ends at w about d_w times as often as at a degree-1
-// vertex); lighter roots are packed into hash tasks of up to `batch` wedges.
+// 4-cycle.  Roots with at most `batch` wedges are packed into hash batches of
+// up to `batch` wedges.  A heavier root goes to direct id windows or to hash
+// ranges, whichever costs less in table operations: direct = one increment
+// per wedge + a table pass per window + two per u and window (cursor and
+// search); hash = about four per wedge + a table pass per range + two per u
+// and range.  Its id ranges of about `batch` wedges each follow the degree
+// mass rp[x] (a wedge ends at w about d_w times as often as at a degree-1
+// vertex).  Windows and ranges are cut into parts of about equal share.
 static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
   gpm_status st = ensure_ren(c, g);
   if (st) return st;
-  const int64_t key = (c->opt_cycle4_mode << 40) ^ c->opt_cycle4_batch;
+  const int64_t key = (c->opt_cycle4_mode << 40) ^ (c->opt_cycle4_split << 32) ^ c->opt_cycle4_batch;
   if (g.cyc_key == key) return GPM_OK;
   if (c->noalloc) return not_prepared(c);
   dev_free(g.cyc_tasks);
   dev_free(g.cyc_roots);
+  dev_free(g.cyc_bounds);
   g.cyc_tasks = nullptr;
   g.cyc_roots = nullptr;
+  g.cyc_bounds = nullptr;
   const HostCSR& R = g.ren_host;
   const int64_t n = R.n;
   std::vector<int32_t> ev(n, 0);
@@ -588,11 +594,12 @@ static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
     const bool c32 = ev[v] >= 65535;
     const int64_t W = c32 ? kCycWindow / 2 : kCycWindow;
     const int64_t K = (v + W - 1) / W;
-    const double cost_direct = (c32 ? (double)v : v / 2.0) + 2.0 * ev[v] * K + (double)E;
-    const double cost_hash = 4.0 * (double)E;
+    const int64_t P = (E + batch - 1) / batch;
+    const double cost_direct = (double)E + (double)K * kCycTableWords + 2.0 * ev[v] * K;
+    const double cost_hash = 4.0 * (double)E + (double)P * kCycTableWords + 2.0 * ev[v] * P;
     const bool dir = c->opt_cycle4_mode == 2 ? E > batch
                    : c->opt_cycle4_mode == 1 ? false
-                   : cost_direct < cost_hash;
+                   : E > batch && cost_direct < cost_hash;
     if (dir) {
       direct.push_back({(int32_t)v, E});
       direct_total += E;
@@ -610,9 +617,12 @@ static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
   std::vector<CycTask> tasks;
   std::vector<int32_t> roots;
   int32_t max_e = 0;
-  // direct roots: parts of consecutive windows, each about a quarter of an
-  // even share of the direct wedges over the workgroups
-  const int64_t share = std::max<int64_t>(direct_total / ((int64_t)c->cus * 4), int64_t(1) << 20);
+  // parts of consecutive windows or ranges, each about 1/split of an even
+  // share of the heavy roots' wedges over the workgroups
+  int64_t heavy_total = direct_total;
+  for (const auto& hr : ranged) heavy_total += hr.first;
+  const int64_t share =
+      std::max<int64_t>(heavy_total / ((int64_t)c->cus * c->opt_cycle4_split), int64_t(1) << 18);
   for (const Direct& d : direct) {
     const bool c32 = ev[d.v] >= 65535;
     const int64_t W = c32 ? kCycWindow / 2 : kCycWindow;
@@ -620,26 +630,29 @@ static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
     const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(K, (d.E + share - 1) / share));
     const int64_t kn = (K + parts - 1) / parts;
     for (int64_t k0 = 0; k0 < K; k0 += kn)
-      tasks.push_back(CycTask{d.v, (int32_t)k0, (int32_t)std::min(kn, K - k0), c32 ? 1 : 0});
+      tasks.push_back(CycTask{d.v, (int32_t)k0, (int32_t)std::min(kn, K - k0), c32 ? kCycWide : 0});
     max_e = std::max(max_e, ev[d.v]);
   }
-  // heavy hash roots: id ranges of about `batch` wedges by degree mass
+  // heavy hash roots: id ranges of about `batch` wedges by degree mass, in
+  // parts of consecutive ranges
+  std::vector<int32_t> bounds;
+  int32_t max_e_ranged = 0;
   for (const auto& hr : ranged) {
     const int32_t v = hr.second;
     const int64_t P = (hr.first + batch - 1) / batch;
-    const int32_t r = (int32_t)roots.size();
-    roots.push_back(v);
-    int32_t x = 0;
-    for (int64_t i = 1; i <= P; ++i) {
-      int32_t y = v;
-      if (i < P) {
-        const int64_t target = (int64_t)((double)R.rp[v] * (double)i / (double)P);
-        y = (int32_t)(std::lower_bound(R.rp.begin(), R.rp.begin() + v, target) - R.rp.begin());
-        y = std::max(y, x);
-      }
-      if (y > x) tasks.push_back(CycTask{-(r + 1), r + 1, x, y});
-      x = y;
+    const int32_t b0 = (int32_t)bounds.size();
+    bounds.push_back(0);
+    for (int64_t i = 1; i < P; ++i) {
+      const int64_t target = (int64_t)((double)R.rp[v] * (double)i / (double)P);
+      int32_t y = (int32_t)(std::lower_bound(R.rp.begin(), R.rp.begin() + v, target) - R.rp.begin());
+      bounds.push_back(std::max(y, bounds.back()));
     }
+    bounds.push_back(v);
+    const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(P, (hr.first + share - 1) / share));
+    const int64_t pn = (P + parts - 1) / parts;
+    for (int64_t r0 = 0; r0 < P; r0 += pn)
+      tasks.push_back(CycTask{v, (int32_t)(b0 + r0), (int32_t)std::min(pn, P - r0), kCycRanges});
+    max_e_ranged = std::max(max_e_ranged, ev[v]);
   }
   // light roots packed into tasks; keys slot * n + w + 1 stay below 2^32
   const int64_t max_slots = std::max<int64_t>(
@@ -656,7 +669,9 @@ static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
     tasks.push_back(CycTask{-(r0 + 1), (int32_t)roots.size(), 0, INT32_MAX});
   }
   g.n_cyc = (int64_t)tasks.size();
-  g.cyc_max_e = max_e;
+  // cursor words per workgroup: two int64 per lower neighbour of a direct
+  // root, three per lower neighbour of a ranged root
+  g.cyc_max_e = std::max(4 * max_e, 6 * max_e_ranged);
   if (!tasks.empty()) {
     st = dev_upload(c, &g.cyc_tasks, tasks.data(), tasks.size());
     if (st) return st;
@@ -665,7 +680,11 @@ static gpm_status ensure_cycle(gpm_ctx* c, Graph& g) {
     st = dev_upload(c, &g.cyc_roots, roots.data(), roots.size());
     if (st) return st;
   }
-  g.bytes += tasks.size() * sizeof(CycTask) + roots.size() * 4;
+  if (!bounds.empty()) {
+    st = dev_upload(c, &g.cyc_bounds, bounds.data(), bounds.size());
+    if (st) return st;
+  }
+  g.bytes += tasks.size() * sizeof(CycTask) + roots.size() * 4 + bounds.size() * 4;
   g.cyc_key = key;
   return GPM_OK;
 }
@@ -999,6 +1018,7 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     J.n_tasks = g.n_cyc;
     J.chunk = 1;
     J.cap = g.cyc_max_e;  // cursor words per workgroup
+    J.bounds = g.cyc_bounds;
     J.n_vertices = (int32_t)n;
     js.jobs.push_back(J);
     js.need_words.push_back(0);
@@ -2112,6 +2132,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "decompose") c->opt_decompose = v != 0;
   else if (k == "edge_terms") { if (v < 0 || v > 1) return fail(c, GPM_E_INVAL, "edge_terms 0..1"); c->opt_edge_terms = v; }
   else if (k == "cycle4_mode") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_mode 0..2"); c->opt_cycle4_mode = v; }
+  else if (k == "cycle4_split") { if (v < 1 || v > 1024) return fail(c, GPM_E_INVAL, "cycle4_split 1..1024"); c->opt_cycle4_split = v; }
   else if (k == "cycle4_batch") { if (v < 2 || v > (1 << 30)) return fail(c, GPM_E_INVAL, "cycle4_batch 2..2^30"); c->opt_cycle4_batch = v; }
   else if (k == "cycle4_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_algo 0..2"); c->opt_cycle4_algo = v; }
   else if (k == "leaf_cap") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "leaf_cap 0..2^20"); c->opt_leaf_cap = v; }
