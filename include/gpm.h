@@ -146,7 +146,15 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *   "chunk"           tasks per queue pop (0 = auto)
  *   "waves_per_cu"    persistent waves per compute unit (0 = auto: 24 for
  *                     local-graph clique launches, 16 otherwise)
- *   "setop"           0 auto, 1 binary search, 2 merge path
+ *   "setop"           how the plan-driven DFS tests membership (Sec. 6.1):
+ *                     1 binary search in global memory, 2 merge path (each
+ *                     chunk of 64 candidates searches only the probed list's
+ *                     range between its first and last candidate, staged in
+ *                     LDS when it holds at most 256 elements; a lane's own
+ *                     leaf walks each list once by galloping), 3 binary
+ *                     search with the top 5 levels (31 pivots) of each probed
+ *                     list's search tree in LDS; 0 = the default, 3
+ *                     (identical counts in every mode)
  *   "clique_lds"      1 = clique kernel keeps frontiers in LDS (default),
  *                     0 = force the generic kernel with HBM frontiers
  *   "rename"          non-clique patterns run on a copy relabelled by
@@ -196,7 +204,8 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *   "autotune"        1 = on the first gpm_count of a (graph, pattern, mode)
  *                     that takes at least "tune_min_ms" (default 20), try the
  *                     knob values of its search space (LDS tile, waves per
- *                     CU, chunk, leaf mode, granularity, renaming) by
+ *                     CU, chunk, leaf mode, set-op mode, granularity,
+ *                     renaming) by
  *                     coordinate descent -- every trial must return the same
  *                     count, else GPM_E_DEVICE -- and reuse the fastest
  *                     values on later calls of that triple

@@ -116,6 +116,14 @@ struct CycTask {
   int32_t c;
 };
 
+// Set operations of the plan-driven DFS (Sec. 6.1): membership probes by
+// binary search in global memory, by a merge-path window of the probed list
+// staged in LDS (a galloping merge in a lane's own leaf), or by binary search
+// with the top levels of the probed list's search tree in LDS.
+constexpr int32_t kSetopBinary = 1;
+constexpr int32_t kSetopMerge = 2;
+constexpr int32_t kSetopBst = 3;
+
 // One unit of work of a persistent launch: a (graph, pattern plan, range of
 // root tasks) triple with its own result slot.
 struct Job {
@@ -144,7 +152,7 @@ struct Job {
                            // zero between launches)
   const int64_t* deg_rp;   // kJobEdgeTerms: offsets of the symmetric graph (degrees)
   int32_t n_vertices;      // kJobCycleBlock: vertices of the graph (hash keys)
-  int32_t pad_;
+  int32_t setop;           // kJobDfs: how set operations probe (kSetop*)
   const int32_t* bounds;   // kJobCycleBlock: id boundaries of the hash ranges
 };
 

@@ -109,6 +109,71 @@ __device__ __forceinline__ int32_t upper_bound(const T* a, int32_t n, K key) {
   return base + (a[base] <= key ? 1 : 0);
 }
 
+// First index i in [lo, n) with a[i] >= key, given a[lo - 1] < key (or lo =
+// 0): one probe when a[lo] >= key already, else an exponential search from
+// lo (the probes stay near lo, where the previous window's slice ended).
+__device__ __forceinline__ int32_t gallop_lb(const int32_t* __restrict__ a, int32_t lo,
+                                             int32_t n, int32_t key) {
+  if (lo >= n || a[lo] >= key) return lo;
+  int32_t base = lo;  // a[base] < key
+  int32_t step = 1;
+  while (base + step < n && a[base + step] < key) {
+    base += step;
+    step <<= 1;
+  }
+  const int32_t hi = min(base + step, n);  // a[hi] >= key, or hi == n
+  return base + 1 + lower_bound(a + base + 1, hi - base - 1, key);
+}
+
+// lower_bound whose first kBstLevels halving steps read their probe values
+// from `piv`: the implicit binary search tree's top levels staged in LDS
+// (Sec. 6.1: the first levels of the search tree kept in the scratchpad).
+// Node t of the tree (1-based heap order: children 2t, 2t + 1) holds the
+// value the search meets after the turns spelled by t's bits, so the result
+// equals lower_bound's.
+constexpr int kBstLevels = 5;
+constexpr int kBstNodes = (1 << kBstLevels) - 1;
+
+__device__ __forceinline__ int32_t lower_bound_bst(const int32_t* __restrict__ a, int32_t n,
+                                                   int32_t key, const int32_t* piv) {
+  if (n <= 0) return 0;
+  int32_t base = 0, node = 1;
+#pragma unroll
+  for (int s = 0; s < kBstLevels; ++s) {
+    if (n <= 1) break;
+    const int32_t half = n >> 1;
+    const bool right = piv[node - 1] < key;
+    base = right ? base + half : base;
+    node = 2 * node + (right ? 1 : 0);
+    n -= half;
+  }
+  while (n > 1) {
+    const int32_t half = n >> 1;
+    base = (a[base + half] < key) ? base + half : base;
+    n -= half;
+  }
+  return base + (a[base] < key ? 1 : 0);
+}
+
+// Stage the kBstNodes pivots of list a[0, n) (lane t < kBstNodes loads node
+// t + 1); nodes the search never reaches are left unset.
+__device__ __forceinline__ void bst_stage(const int32_t* __restrict__ a, int32_t n, int32_t* piv) {
+  const int p = lane_id();
+  if (p < kBstNodes) {
+    const int32_t q = p + 1;
+    const int lvl = 31 - __clz(q);
+    int32_t nn = n, base = 0;
+    bool live = true;
+    for (int i = lvl - 1; i >= 0 && live; --i) {
+      if (nn <= 1) { live = false; break; }
+      const int32_t half = nn >> 1;
+      if ((q >> i) & 1) base += half;
+      nn -= half;
+    }
+    if (live && nn > 1) piv[p] = a[base + (nn >> 1)];
+  }
+}
+
 // Instrumented builds only (CE = true): the method's own work, counted the
 // same way in every lane (summed over the wave, then divided by 64).
 struct ElemCounter {
@@ -867,6 +932,18 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
 // generic plan-driven DFS (Alg. 1 generalised by the plan table)
 // ---------------------------------------------------------------------------
 
+// How a DFS set operation probes its lists (Sec. 6.1): plain binary search
+// in global memory; a merge-path window (for each chunk of 64 base elements,
+// the probed list's range between the chunk's first and last element staged
+// in LDS when it holds at most kMergeWin elements, and searched there; for a
+// lane's own leaf, a galloping merge along each list); or binary search with
+// the top kBstLevels of each probed list's search tree in LDS.
+struct SetOp {
+  int32_t mode;            // kSetopBinary, kSetopMerge, kSetopBst
+  int32_t* lds;            // the wave's area: kMergeWin window | kBstNodes pivots per list
+};
+constexpr int kMergeWin = 256;
+
 struct DfsState {
   int32_t v[kMaxK];        // matched data vertices by depth
   int32_t sz[kMaxK];       // candidate set size by depth
@@ -884,7 +961,7 @@ template <bool STORE, bool CE>
 __device__ __forceinline__ int32_t dfs_level(const int64_t* __restrict__ rp,
                                              const int32_t* __restrict__ col,
                                              const LevelPlan& L, DfsState& st, int d,
-                                             int32_t* out, ElemCounter& ec) {
+                                             int32_t* out, const SetOp& so, ElemCounter& ec) {
   int32_t bound = INT_MAX;
   for (int j = 0; j < d; ++j)
     if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
@@ -938,21 +1015,84 @@ __device__ __forceinline__ int32_t dfs_level(const int64_t* __restrict__ rp,
   }
 
   const int l = lane_id();
+  int32_t* piv = so.lds + kMergeWin;
+  if (so.mode == kSetopBst) {
+    // the top of each probed list's search tree, once for the whole level
+    int qq = 0;
+    for (int q = 0; q < L.n_int; ++q) {
+      if (q == base_i) continue;
+      const int32_t vj = st.v[L.int_lv[q]];
+      bst_stage(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), piv + kBstNodes * qq++);
+    }
+    for (int q = 0; q < L.n_sub; ++q) {
+      const int32_t vj = st.v[L.sub_lv[q]];
+      bst_stage(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), piv + kBstNodes * qq++);
+    }
+    wave_sync_mem();
+  }
   int32_t total = 0;
   for (int32_t ib = 0; ib < blen; ib += 64) {
     int32_t i = ib + l;
     bool keep = i < blen;
     int32_t x = keep ? base[i] : 0;
-    for (int q = 0; q < L.n_int && keep; ++q) {
-      if (q == base_i) continue;
-      int32_t vj = st.v[L.int_lv[q]];
-      const int32_t* N = col + rp[vj];
-      keep = member(N, (int32_t)(rp[vj + 1] - rp[vj]), x);
-    }
-    for (int q = 0; q < L.n_sub && keep; ++q) {
-      int32_t vj = st.v[L.sub_lv[q]];
-      const int32_t* N = col + rp[vj];
-      keep = !member(N, (int32_t)(rp[vj + 1] - rp[vj]), x);
+    if (so.mode == kSetopMerge) {
+      // each probed list's range between the chunk's first and last element
+      const int32_t xf = uni(base[ib]);
+      const int32_t xl = uni(base[min(ib + 63, blen - 1)]);
+      for (int q = 0; q < L.n_int + L.n_sub; ++q) {
+        const bool sub = q >= L.n_int;
+        if (!sub && q == base_i) continue;
+        const int32_t vj = st.v[sub ? L.sub_lv[q - L.n_int] : L.int_lv[q]];
+        const int32_t* N = col + rp[vj];
+        const int32_t n = (int32_t)(rp[vj + 1] - rp[vj]);
+        const int32_t p0 = uni(lower_bound(N, n, xf));
+        const int32_t wl = uni(upper_bound(N, n, xl)) - p0;
+        bool m;
+        if (wl <= kMergeWin) {
+          for (int32_t t = l; t < wl; t += 64) so.lds[t] = N[p0 + t];
+          wave_sync_mem();
+          m = member(so.lds, wl, x);
+          wave_sync_mem();
+        } else {
+          m = member(N + p0, wl, x);
+        }
+        keep = keep && (sub ? !m : m);
+      }
+    } else if (so.mode == kSetopBst) {
+      int qq = 0;
+      for (int q = 0; q < L.n_int; ++q) {
+        if (q == base_i) continue;
+        const int32_t vj = st.v[L.int_lv[q]];
+        const int32_t* N = col + rp[vj];
+        const int32_t n = (int32_t)(rp[vj + 1] - rp[vj]);
+        if (keep) {
+          const int32_t p = lower_bound_bst(N, n, x, piv + kBstNodes * qq);
+          keep = p < n && N[p] == x;
+        }
+        ++qq;
+      }
+      for (int q = 0; q < L.n_sub; ++q) {
+        const int32_t vj = st.v[L.sub_lv[q]];
+        const int32_t* N = col + rp[vj];
+        const int32_t n = (int32_t)(rp[vj + 1] - rp[vj]);
+        if (keep) {
+          const int32_t p = lower_bound_bst(N, n, x, piv + kBstNodes * qq);
+          keep = !(p < n && N[p] == x);
+        }
+        ++qq;
+      }
+    } else {
+      for (int q = 0; q < L.n_int && keep; ++q) {
+        if (q == base_i) continue;
+        int32_t vj = st.v[L.int_lv[q]];
+        const int32_t* N = col + rp[vj];
+        keep = member(N, (int32_t)(rp[vj + 1] - rp[vj]), x);
+      }
+      for (int q = 0; q < L.n_sub && keep; ++q) {
+        int32_t vj = st.v[L.sub_lv[q]];
+        const int32_t* N = col + rp[vj];
+        keep = !member(N, (int32_t)(rp[vj + 1] - rp[vj]), x);
+      }
     }
     for (int j = 0; j < d && keep; ++j)
       if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
@@ -987,7 +1127,8 @@ template <bool CE>
 __device__ __forceinline__ bool leaf_serial(const int64_t* __restrict__ rp,
                                             const int32_t* __restrict__ col,
                                             const LevelPlan& L, const DfsState& st, int d,
-                                            int32_t cap, uint64_t& count, ElemCounter& ec) {
+                                            int32_t cap, const SetOp& so, uint64_t& count,
+                                            ElemCounter& ec) {
   int32_t bound = INT_MAX;
   for (int j = 0; j < d; ++j)
     if ((L.bound_mask >> j) & 1) bound = min(bound, st.v[j]);
@@ -1019,21 +1160,56 @@ __device__ __forceinline__ bool leaf_serial(const int64_t* __restrict__ rp,
   }
   if (blen > cap) return false;
   uint64_t c = 0;
-  for (int32_t i = 0; i < blen; ++i) {
-    const int32_t x = base[i];
-    bool keep = true;
-    for (int q = 0; q < L.n_int && keep; ++q) {
-      if (q == base_i) continue;
-      int32_t vj = st.v[L.int_lv[q]];
-      keep = member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+  if (so.mode == kSetopMerge) {
+    // the base ascends, so each probed list is walked once, galloping from
+    // where the previous element left it
+    int32_t pi[kMaxK], ps[kMaxK];
+#pragma unroll
+    for (int q = 0; q < kMaxK; ++q) pi[q] = ps[q] = 0;
+    for (int32_t i = 0; i < blen; ++i) {
+      const int32_t x = base[i];
+      bool keep = true;
+#pragma unroll
+      for (int q = 0; q < kMaxK; ++q) {
+        if (q < L.n_int && q != base_i && keep) {
+          const int32_t vj = st.v[L.int_lv[q]];
+          const int32_t* N = col + rp[vj];
+          const int32_t n = (int32_t)(rp[vj + 1] - rp[vj]);
+          pi[q] = gallop_lb(N, pi[q], n, x);
+          keep = pi[q] < n && N[pi[q]] == x;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kMaxK; ++q) {
+        if (q < L.n_sub && keep) {
+          const int32_t vj = st.v[L.sub_lv[q]];
+          const int32_t* N = col + rp[vj];
+          const int32_t n = (int32_t)(rp[vj + 1] - rp[vj]);
+          ps[q] = gallop_lb(N, ps[q], n, x);
+          keep = !(ps[q] < n && N[ps[q]] == x);
+        }
+      }
+      for (int j = 0; j < d && keep; ++j)
+        if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
+      c += keep ? 1u : 0u;
     }
-    for (int q = 0; q < L.n_sub && keep; ++q) {
-      int32_t vj = st.v[L.sub_lv[q]];
-      keep = !member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+  } else {
+    for (int32_t i = 0; i < blen; ++i) {
+      const int32_t x = base[i];
+      bool keep = true;
+      for (int q = 0; q < L.n_int && keep; ++q) {
+        if (q == base_i) continue;
+        int32_t vj = st.v[L.int_lv[q]];
+        keep = member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+      }
+      for (int q = 0; q < L.n_sub && keep; ++q) {
+        int32_t vj = st.v[L.sub_lv[q]];
+        keep = !member(col + rp[vj], (int32_t)(rp[vj + 1] - rp[vj]), x);
+      }
+      for (int j = 0; j < d && keep; ++j)
+        if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
+      c += keep ? 1u : 0u;
     }
-    for (int j = 0; j < d && keep; ++j)
-      if ((L.excl_mask >> j) & 1) keep = x != st.v[j];
-    c += keep ? 1u : 0u;
   }
   if (CE) {
     uint64_t e = (uint64_t)blen;
@@ -1059,7 +1235,7 @@ __device__ __forceinline__ bool leaf_serial(const int64_t* __restrict__ rp,
 template <bool CE>
 __device__ uint64_t leaf_bulk(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                               const Plan& P, int d, DfsState& st, int32_t cap, int32_t* defq,
-                              ElemCounter& ec) {
+                              const SetOp& so, ElemCounter& ec) {
   const LevelPlan& Ld = P.lv[d];
   const LevelPlan& L = P.lv[d + 1];
   const int32_t sz = uni(st.sz[d]);
@@ -1075,7 +1251,7 @@ __device__ uint64_t leaf_bulk(const int64_t* __restrict__ rp, const int32_t* __r
     if (act) {
       st.v[d] = x;
       uint64_t cnt = 0;
-      if (leaf_serial<CE>(rp, col, L, st, d + 1, cap, cnt, ec)) c += cnt;
+      if (leaf_serial<CE>(rp, col, L, st, d + 1, cap, so, cnt, ec)) c += cnt;
       else defer = true;
     }
     const uint64_t dm = wave_ballot(defer);
@@ -1085,7 +1261,7 @@ __device__ uint64_t leaf_bulk(const int64_t* __restrict__ rp, const int32_t* __r
       const int nd = (int)__popcll(dm);
       for (int q = 0; q < nd; ++q) {
         st.v[d] = uni(defq[q]);
-        c += (uint64_t)dfs_level<false, CE>(rp, col, L, st, d + 1, nullptr, ec);
+        c += (uint64_t)dfs_level<false, CE>(rp, col, L, st, d + 1, nullptr, so, ec);
       }
       wave_sync_mem();
     }
@@ -1100,28 +1276,28 @@ template <bool CE>
 __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                              const Plan& P, int32_t v0, int32_t v1, int32_t* fb,
                              int32_t cap, int32_t leaf_cap, DfsState& st, int32_t* defq,
-                             ElemCounter& ec) {
+                             const SetOp& so, ElemCounter& ec) {
   const int k = P.k;
   st.v[0] = v0;
   st.v[1] = v1;
-  if (k == 3) return (uint64_t)dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, ec);
+  if (k == 3) return (uint64_t)dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, so, ec);
   uint64_t c = 0;
   int d = 2;
   {
     int32_t* out = fb + (size_t)(P.store_slot[2] < 0 ? 0 : P.store_slot[2]) * cap;
-    st.sz[2] = uni(dfs_level<true, CE>(rp, col, P.lv[2], st, 2, out, ec));
+    st.sz[2] = uni(dfs_level<true, CE>(rp, col, P.lv[2], st, 2, out, so, ec));
     st.ix[2] = 0;
   }
   for (;;) {
     if (d == k - 2) {
       if (leaf_cap > 0) {
-        c += leaf_bulk<CE>(rp, col, P, d, st, leaf_cap, defq, ec);
+        c += leaf_bulk<CE>(rp, col, P, d, st, leaf_cap, defq, so, ec);
       } else {
         for (int32_t i = 0; i < st.sz[d]; ++i) {
           int32_t x = uni(st.set[d][i]);
           if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) continue;
           st.v[d] = x;
-          c += (uint64_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, ec);
+          c += (uint64_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, so, ec);
         }
       }
       if (d == 2) break;
@@ -1143,7 +1319,7 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
     st.v[d] = x;
     ++d;
     int32_t* out = fb + (size_t)(P.store_slot[d] < 0 ? 0 : P.store_slot[d]) * cap;
-    st.sz[d] = uni(dfs_level<true, CE>(rp, col, P.lv[d], st, d, out, ec));
+    st.sz[d] = uni(dfs_level<true, CE>(rp, col, P.lv[d], st, d, out, so, ec));
     st.ix[d] = 0;
   }
   return c;
@@ -1528,6 +1704,8 @@ gpm_persistent(KernelArgs a) {
   extern __shared__ int32_t lds[];
   __shared__ int32_t lds_state[kWavesPerBlock][2 * kMaxK];
   __shared__ int32_t dfs_defq[(KINDS & kKindDfs) ? kWavesPerBlock : 1][64];
+  __shared__ int32_t dfs_setop[(KINDS & kKindDfs) ? kWavesPerBlock : 1]
+                              [(KINDS & kKindDfs) ? kMergeWin + kBstNodes * kMaxK : 1];
   const int w = threadIdx.x >> 6;
   int32_t* my = lds + (size_t)w * a.lds_words;
   int32_t* st_words = lds_state[w];
@@ -1611,12 +1789,13 @@ gpm_persistent(KernelArgs a) {
           for (int32_t e = 0; e < end; ++e) {
             int32_t v1 = uni(N0[e]);
             acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, J.leaf_cap, st,
-                                   dfs_defq[w], ec);
+                                   dfs_defq[w], SetOp{J.setop, dfs_setop[w]}, ec);
           }
         } else {
           int32_t v0 = uni(J.task_src[t]);
           int32_t v1 = uni(J.task_dst[t]);
           acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, J.leaf_cap, st, dfs_defq[w],
+                                 SetOp{J.setop, dfs_setop[w]},
                                  ec);
         }
       }
@@ -1787,22 +1966,6 @@ struct CycShared {
 
 __device__ __forceinline__ uint32_t cyc_hash(uint32_t key) {
   return (key * 2654435761u) >> (32 - kCycSlotBits);
-}
-
-// First index i in [lo, n) with a[i] >= key, given a[lo - 1] < key (or lo =
-// 0): one probe when a[lo] >= key already, else an exponential search from
-// lo (the probes stay near lo, where the previous window's slice ended).
-__device__ __forceinline__ int32_t gallop_lb(const int32_t* __restrict__ a, int32_t lo,
-                                             int32_t n, int32_t key) {
-  if (lo >= n || a[lo] >= key) return lo;
-  int32_t base = lo;  // a[base] < key
-  int32_t step = 1;
-  while (base + step < n && a[base + step] < key) {
-    base += step;
-    step <<= 1;
-  }
-  const int32_t hi = min(base + step, n);  // a[hi] >= key, or hi == n
-  return base + 1 + lower_bound(a + base + 1, hi - base - 1, key);
 }
 
 // One batch of up to 64 slices per wave: lane l holds the slice

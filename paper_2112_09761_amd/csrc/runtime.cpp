@@ -732,6 +732,13 @@ static int64_t lgs_block_max_vertices(const gpm_ctx* c) {
   return d;
 }
 
+// How the DFS set operations probe (option "setop"; 0 = the default: binary
+// search with the search tree's top levels in LDS, measured fastest of the
+// three on R-MAT and Chung-Lu graphs).
+static int32_t setop_mode(const gpm_ctx* c) {
+  return c->opt_setop > 0 ? (int32_t)c->opt_setop : kSetopBst;
+}
+
 static int lds_tile(const gpm_ctx* c) {
   return c->opt_lds_tile > 0 ? (int)c->opt_lds_tile : 512;
 }
@@ -989,6 +996,7 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
       st = build_plan(p, mode, true, &hp, &err);
       if (st) return fail(c, st, err);
       J.kind = kJobDfs;
+      J.setop = setop_mode(c);
       J.chunk = default_chunk(c, kJobDfs);
       J.plan = (int32_t)js.plans.size();
       js.plans.push_back(hp.plan);
@@ -1037,6 +1045,7 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
   const int64_t cap = std::max<int64_t>(V.max_deg, 1);
   Job J{};
   J.kind = kJobDfs;
+  J.setop = setop_mode(c);
   J.leaf_cap = (int32_t)c->opt_leaf_cap;
   J.k = p.k;
   J.rp = V.rp;
@@ -1094,6 +1103,7 @@ static int64_t* knob(gpm_ctx* c, const std::string& k) {
   if (k == "leaf_cap") return &c->opt_leaf_cap;
   if (k == "rename") return &c->opt_rename;
   if (k == "lds_tile") return &c->opt_lds_tile;
+  if (k == "setop") return &c->opt_setop;
   return nullptr;
 }
 
@@ -1106,8 +1116,8 @@ static std::vector<std::pair<std::string, std::vector<int64_t>>> tune_space(cons
     return {{"lgs_tile", {128, 64, 192}}, {"waves_per_cu", {0, 16, 32}}, {"chunk", {0, 2}}};
   if (clique) return {{"lds_tile", {0, 256, 128}}, {"chunk", {0, 4, 16}}, {"waves_per_cu", {16, 12}}};
   (void)mode;
-  return {{"leaf_cap", {128, 0, 32, 512}}, {"chunk", {0, 2, 32}}, {"granularity", {0, 1}},
-          {"rename", {1, 0}}, {"waves_per_cu", {16, 12}}};
+  return {{"leaf_cap", {128, 0, 32, 512}}, {"setop", {0, 1, 2}}, {"chunk", {0, 2, 32}},
+          {"granularity", {0, 1}}, {"rename", {1, 0}}, {"waves_per_cu", {16, 12}}};
 }
 
 static std::string tune_key(int32_t gid, const gpm_pattern& p, int mode) {
@@ -2121,7 +2131,7 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   if (k == "granularity") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "granularity 0..2"); c->opt_granularity = v; }
   else if (k == "chunk") { if (v < 0 || v > (1 << 20)) return fail(c, GPM_E_INVAL, "chunk"); c->opt_chunk = v; }
   else if (k == "waves_per_cu") { if (v < 0 || v > 32) return fail(c, GPM_E_INVAL, "waves_per_cu 0..32"); c->opt_waves_per_cu = v; }
-  else if (k == "setop") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "setop 0..2"); c->opt_setop = v; }
+  else if (k == "setop") { if (v < 0 || v > 3) return fail(c, GPM_E_INVAL, "setop 0..3"); c->opt_setop = v; }
   else if (k == "clique_lds") c->opt_clique_lds = v != 0;
   else if (k == "lds_tile") { if (v < 0 || v > 4096) return fail(c, GPM_E_INVAL, "lds_tile 0..4096"); c->opt_lds_tile = v; }
   else if (k == "rename") { if (v < 0 || v > 1) return fail(c, GPM_E_INVAL, "rename 0..1"); c->opt_rename = v; }

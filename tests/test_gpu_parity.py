@@ -127,10 +127,13 @@ def test_random_patterns(ctx, oracle, seed):
         for k in (3, 4, 5, 6):
             pat = random_pattern(rng, k)
             for mode in (V, E):
-                got = ctx.count(gid, pat, mode)
                 exp = oracle.count_embed(g, pat, mode == V)
-                assert got == exp, (pat, mode, got, exp)
+                for setop in (1, 2, 3):          # every set-op variant (Sec. 6.1)
+                    ctx.set_option("setop", setop)
+                    got = ctx.count(gid, pat, mode)
+                    assert got == exp, (pat, mode, setop, got, exp)
     finally:
+        ctx.set_option("setop", 0)
         ctx.unload(gid)
 
 
@@ -145,10 +148,13 @@ def test_random_patterns_seven_eight(ctx, oracle, seed):
         for k in (7, 8):
             pat = random_pattern(rng, k)
             for mode in (V, E):
-                got = ctx.count(gid, pat, mode)
                 exp = oracle.count_embed(g, pat, mode == V)
-                assert got == exp, (pat, mode, got, exp)
+                for setop in (1, 2, 3):
+                    ctx.set_option("setop", setop)
+                    got = ctx.count(gid, pat, mode)
+                    assert got == exp, (pat, mode, setop, got, exp)
     finally:
+        ctx.set_option("setop", 0)
         ctx.unload(gid)
 
 
@@ -183,7 +189,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                           ("lgs_tile", [64, 256]), ("lgs_max", [64, 100]),
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
                           ("rename", [0]), ("cycle4_algo", [1, 2]), ("decompose", [0]),
-                          ("edge_terms", [1]), ("cycle4_mode", [1, 2]),
+                          ("edge_terms", [1]), ("cycle4_mode", [1, 2]), ("setop", [1, 2, 3]),
                           ("cycle4_batch", [16, 1 << 20])]:
             for v in vals:
                 ctx.set_option(opt, v)
@@ -194,7 +200,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                                  "clique_lds": 1, "granularity": 0, "clique_algo": 0,
                                  "lgs_tile": 128, "lgs_max": 2048, "lgs_split": 1,
                                  "leaf_cap": 128, "rename": 1, "cycle4_algo": 0,
-                                 "decompose": 1, "edge_terms": 0, "cycle4_mode": 0,
+                                 "decompose": 1, "edge_terms": 0, "cycle4_mode": 0, "setop": 0,
                                  "cycle4_batch": 8192}[opt])
     finally:
         ctx.unload(gid)
