@@ -184,11 +184,17 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *   "cycle4_batch"    wedges per 4-cycle hash task (2..2^30, default 8192);
  *                     a task whose distinct endpoints overflow the LDS table
  *                     splits on the device (identical counts)
- *   "decompose"       1 (default) = wedge, 3-star, 4-path, tailed-triangle
- *                     and diamond counts (both modes) come from per-vertex
- *                     and per-edge terms (plus the 4-clique, triangle or
- *                     4-cycle count their induced forms need: counting-only
- *                     pruning, Sec. 5.4 (1)); 0 = the DFS plan (identical
+ *   "decompose"       counting-only pruning (Sec. 5.4 (1)), 1 (default):
+ *                     wedge, 3-star, 4-path, tailed-triangle and diamond
+ *                     counts (both modes) come from per-vertex and per-edge
+ *                     terms (plus the 4-clique, triangle or 4-cycle count
+ *                     their induced forms need); any other edge-induced
+ *                     count whose pattern has r >= 2 pairwise non-adjacent
+ *                     twin vertices (same neighbours) beside a connected
+ *                     rest of >= 2 vertices walks only the rest and adds
+ *                     ext * C(n, r) per match of it (n: the twins' common
+ *                     candidate set, ext: the twins' orderings its symmetry
+ *                     restrictions allow); 0 = the plain DFS plan (identical
  *                     counts)
  *   "edge_terms"      per-edge motif terms (4-motifs, decomposed counts):
  *                     0 (default) = the k = 3 local-graph search adds each
@@ -279,6 +285,11 @@ typedef struct {
     int32_t order[GPM_MAX_K];    /* pattern vertex matched at depth d        */
     int32_t restrictions[2 * GPM_MAX_PATTERN_EDGES];  /* pairs (a, b):
                                     v_a > v_b, pattern vertex ids            */
+    int32_t count_only_r;        /* counting-only pruning of the count plan
+                                    (option "decompose", Sec. 5.4 (1)): the
+                                    last r pattern vertices of the order are
+                                    twins counted as C(n, r) at one leaf (0:
+                                    none; edge-induced non-cliques only)     */
 } gpm_plan_info;
 
 gpm_status gpm_plan(const gpm_pattern *pattern, int mode, gpm_plan_info *out);

@@ -38,10 +38,13 @@ constexpr uint8_t kLvSlice = 2;   // the set is a bounded prefix of one list;
                                   // iterate it in place, skipping excl_mask
 
 struct Plan {
-  int32_t k;
+  int32_t k;               // depths walked (the leaf is depth k - 1)
   int32_t root_bound;      // 1: root edges (v0, v1) need v1 < v0
   int32_t n_store;         // number of stored depths (frontier buffers)
-  int32_t pad;
+  int32_t leaf_choose;     // 0: the leaf counts its set; else r | ext << 8:
+                           // the leaf set stands for the pattern's last r
+                           // vertices (counting-only pruning) and adds
+                           // ext * C(|set|, r)
   int8_t store_slot[kMaxK];  // depth -> frontier buffer index, -1 if none
   LevelPlan lv[kMaxK];
 };

@@ -941,6 +941,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
 struct SetOp {
   int32_t mode;            // kSetopBinary, kSetopMerge, kSetopBst
   int32_t* lds;            // the wave's area: kMergeWin window | kBstNodes pivots per list
+  int32_t choose;          // the plan's leaf_choose (counting-only leaf)
 };
 constexpr int kMergeWin = 256;
 
@@ -1112,6 +1113,50 @@ __device__ __forceinline__ int32_t dfs_level(const int64_t* __restrict__ rp,
   return total;
 }
 
+// C(n, r) mod 2^64 for r <= kMaxK - 2: the factors of r! are divided out of
+// the r numerator terms first (r consecutive integers hold them all), so the
+// product of what remains is exact modulo 2^64.
+__device__ __forceinline__ uint64_t choose_mod64(uint64_t n, int r) {
+  if (n < (uint64_t)r) return 0;
+  uint64_t t[kMaxK];
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) t[i] = i < r ? n - (uint64_t)i : 1;
+  for (int j = 2; j <= r; ++j) {
+    int m = j;
+    for (int p = 2; p <= 5; ++p)
+      while (m % p == 0) {
+        m /= p;
+#pragma unroll
+        for (int i = 0; i < kMaxK; ++i)
+          if (i < r && t[i] % (uint64_t)p == 0) {
+            t[i] /= (uint64_t)p;
+            break;
+          }
+      }
+  }
+  uint64_t c = 1;
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) c *= t[i];
+  return c;
+}
+
+// What a leaf set of size n counts: n, or under counting-only pruning
+// (Plan::leaf_choose = r | ext << 8) ext * C(n, r).
+__device__ __forceinline__ uint64_t leaf_term(uint64_t n, int32_t choose) {
+  if (choose == 0) return n;
+  return (uint64_t)(choose >> 8) * choose_mod64(n, choose & 0xff);
+}
+
+// Leaf of a wave-wide set operation: the lanes' shares of the set size;
+// under counting-only pruning the term of the whole set goes to lane 0.
+__device__ __forceinline__ uint64_t leaf_wave(int32_t share, int32_t choose) {
+  if (choose == 0) return (uint64_t)share;
+  int32_t n = share;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+  return lane_id() == 0 ? leaf_term((uint64_t)n, choose) : 0;
+}
+
 __device__ __forceinline__ bool slice_excluded(const LevelPlan& L, const DfsState& st,
                                                int d, int32_t x) {
   for (int j = 0; j < d; ++j)
@@ -1154,7 +1199,7 @@ __device__ __forceinline__ bool leaf_serial(const int64_t* __restrict__ rp,
     for (int j = 0; j < d; ++j)
       if ((L.excl_mask >> j) & 1)
         if (st.v[j] < bound && member(base, blen, st.v[j])) --c;
-    count += (uint64_t)c;
+    count += leaf_term((uint64_t)c, so.choose);
     if (CE) { ec.elems += (uint64_t)blen * 64; ec.fetches += 64; }
     return true;
   }
@@ -1225,7 +1270,7 @@ __device__ __forceinline__ bool leaf_serial(const int64_t* __restrict__ rp,
     ec.elems += e * 64;
     ec.fetches += (uint64_t)(1 + n_probe + L.n_sub) * 64;
   }
-  count += c;
+  count += leaf_term(c, so.choose);
   return true;
 }
 
@@ -1261,7 +1306,7 @@ __device__ uint64_t leaf_bulk(const int64_t* __restrict__ rp, const int32_t* __r
       const int nd = (int)__popcll(dm);
       for (int q = 0; q < nd; ++q) {
         st.v[d] = uni(defq[q]);
-        c += (uint64_t)dfs_level<false, CE>(rp, col, L, st, d + 1, nullptr, so, ec);
+        c += leaf_wave(dfs_level<false, CE>(rp, col, L, st, d + 1, nullptr, so, ec), so.choose);
       }
       wave_sync_mem();
     }
@@ -1280,7 +1325,7 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
   const int k = P.k;
   st.v[0] = v0;
   st.v[1] = v1;
-  if (k == 3) return (uint64_t)dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, so, ec);
+  if (k == 3) return leaf_wave(dfs_level<false, CE>(rp, col, P.lv[2], st, 2, nullptr, so, ec), so.choose);
   uint64_t c = 0;
   int d = 2;
   {
@@ -1297,7 +1342,8 @@ __device__ uint64_t dfs_root(const int64_t* __restrict__ rp, const int32_t* __re
           int32_t x = uni(st.set[d][i]);
           if ((P.lv[d].flags & kLvSlice) && slice_excluded(P.lv[d], st, d, x)) continue;
           st.v[d] = x;
-          c += (uint64_t)dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, so, ec);
+          c += leaf_wave(dfs_level<false, CE>(rp, col, P.lv[d + 1], st, d + 1, nullptr, so, ec),
+                         so.choose);
         }
       }
       if (d == 2) break;
@@ -1789,13 +1835,13 @@ gpm_persistent(KernelArgs a) {
           for (int32_t e = 0; e < end; ++e) {
             int32_t v1 = uni(N0[e]);
             acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, J.leaf_cap, st,
-                                   dfs_defq[w], SetOp{J.setop, dfs_setop[w]}, ec);
+                                   dfs_defq[w], SetOp{J.setop, dfs_setop[w], P.leaf_choose}, ec);
           }
         } else {
           int32_t v0 = uni(J.task_src[t]);
           int32_t v1 = uni(J.task_dst[t]);
           acc[0] += dfs_root<CE>(rp, col, P, v0, v1, fb, J.cap, J.leaf_cap, st, dfs_defq[w],
-                                 SetOp{J.setop, dfs_setop[w]},
+                                 SetOp{J.setop, dfs_setop[w], P.leaf_choose},
                                  ec);
         }
       }

@@ -84,17 +84,25 @@ static std::vector<std::array<int8_t, kMaxK>> automorphisms(int k, bool adj[kMax
 // repeatedly take the unmatched vertex with the most matched neighbours
 // (ties: higher degree, then lower id).  Every depth > 0 is adjacent to an
 // earlier depth, and depth 1 is adjacent to depth 0 (edge-rooted tasks).
-static void matching_order(int k, bool adj[kMaxK][kMaxK], int order[kMaxK]) {
+static void matching_order(int k, bool adj[kMaxK][kMaxK], int order[kMaxK],
+                           uint32_t last = 0) {
+  // `last`: vertices kept for the end of the order (in id order)
   int deg[kMaxK] = {};
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) deg[i] += adj[i][j];
   bool used[kMaxK] = {};
-  int first = 0;
-  for (int i = 1; i < k; ++i)
-    if (deg[i] > deg[first]) first = i;
+  int first = -1;
+  for (int i = 0; i < k; ++i)
+    if (!((last >> i) & 1u) && (first < 0 || deg[i] > deg[first])) first = i;
   order[0] = first;
   used[first] = true;
-  for (int d = 1; d < k; ++d) {
+  int kp = k - __builtin_popcount(last);
+  for (int i = 0, d = kp; i < k; ++i)
+    if ((last >> i) & 1u) {
+      order[d++] = i;
+      used[i] = true;
+    }
+  for (int d = 1; d < kp; ++d) {
     int best = -1, bc = -1, bd = -1;
     for (int v = 0; v < k; ++v) {
       if (used[v]) continue;
@@ -112,7 +120,58 @@ static void matching_order(int k, bool adj[kMaxK][kMaxK], int order[kMaxK]) {
   }
 }
 
-int build_plan(const gpm_pattern& p, int mode, bool on_dag, HostPlan* out, std::string* err) {
+// Counting-only pruning (Sec. 5.4 (1), by pattern decomposition): the largest
+// set S of r >= 2 pairwise non-adjacent pattern vertices with the same
+// neighbours (twins) such that the rest of the pattern is connected and has
+// at least two vertices.  Matched last, S's vertices all draw from one
+// candidate set C (the same intersection, the same bounds from earlier
+// vertices, the same exclusions), so in edge-induced mode the matches that
+// extend one prefix number ext * C(|C|, r), ext being the orderings of S
+// that its symmetry restrictions allow.  Returns S as a bit mask (0: none).
+static uint32_t twin_suffix(int k, bool adj[kMaxK][kMaxK]) {
+  uint32_t best = 0;
+  int best_r = 1;
+  for (int a = 0; a < k; ++a) {
+    uint32_t cls = 0;
+    for (int b = 0; b < k; ++b) {
+      if (adj[a][b]) continue;
+      bool same = true;
+      for (int x = 0; x < k && same; ++x)
+        if (x != a && x != b && adj[a][x] != adj[b][x]) same = false;
+      if (same) cls |= 1u << b;   // includes a itself
+    }
+    // the whole class, or all but one of it, as S
+    for (int drop = -1; drop < k; ++drop) {
+      uint32_t S = cls;
+      if (drop >= 0) {
+        if (!((cls >> drop) & 1u)) continue;
+        S &= ~(1u << drop);
+      }
+      const int r = __builtin_popcount(S);
+      if (r <= best_r || k - r < 2) continue;
+      // the rest connected
+      uint32_t rest = ((1u << k) - 1) & ~S;
+      int start = __builtin_ctz(rest);
+      uint32_t seen = 1u << start, frontier = seen;
+      while (frontier) {
+        int x = __builtin_ctz(frontier);
+        frontier &= frontier - 1;
+        for (int y = 0; y < k; ++y)
+          if (adj[x][y] && ((rest >> y) & 1u) && !((seen >> y) & 1u)) {
+            seen |= 1u << y;
+            frontier |= 1u << y;
+          }
+      }
+      if (seen != rest) continue;
+      best = S;
+      best_r = r;
+    }
+  }
+  return best;
+}
+
+int build_plan(const gpm_pattern& p, int mode, bool on_dag, HostPlan* out, std::string* err,
+               bool count_only) {
   int st = validate_pattern(p, err);
   if (st) return st;
   HostPlan hp;
@@ -163,7 +222,9 @@ int build_plan(const gpm_pattern& p, int mode, bool on_dag, HostPlan* out, std::
     return GPM_OK;
   }
 
-  matching_order(k, adj, hp.order);
+  const uint32_t suffix =
+      (count_only && mode == GPM_EDGE_INDUCED && !hp.clique) ? twin_suffix(k, adj) : 0;
+  matching_order(k, adj, hp.order, suffix);
   int depth_of[kMaxK];
   for (int d = 0; d < k; ++d) depth_of[hp.order[d]] = d;
 
@@ -265,6 +326,42 @@ int build_plan(const gpm_pattern& p, int mode, bool on_dag, HostPlan* out, std::
   }
   P.n_store = ns;
   hp.n_buffers = ns;
+
+  if (suffix) {
+    // the leaf at depth kp = k - r stands for depths kp .. k-1; its level
+    // (like theirs) intersects the same lists under the same bounds and
+    // exclusions from depths below kp
+    const int r = __builtin_popcount(suffix);
+    const int kp = k - r;
+    const uint8_t below = (uint8_t)((1u << kp) - 1);
+    bool ok = true;
+    for (int l = kp + 1; l < k && ok; ++l)
+      ok = (intm[l] & below) == (intm[kp] & below) && !(intm[l] & ~below) &&
+           (bnd[l] & below) == (bnd[kp] & below) && subm[l] == 0;
+    if (ok) {
+      // orderings of the r suffix vertices allowed by their restrictions
+      int perm[kMaxK];
+      for (int i = 0; i < r; ++i) perm[i] = i;
+      int ext = 0;
+      do {  // perm[i] = rank of the value at depth kp + i
+        bool fine = true;
+        for (int a = 0; a < r && fine; ++a)
+          for (int b = 0; b < r && fine; ++b)
+            if (((bnd[kp + b] >> (kp + a)) & 1u) && !(perm[a] > perm[b])) fine = false;
+        ext += fine ? 1 : 0;
+      } while (std::next_permutation(perm, perm + r));
+      LevelPlan& L = P.lv[kp];
+      L.flags = 0;  // count-only
+      for (int l = kp; l < kMaxK; ++l) P.store_slot[l] = -1;
+      int n2 = 0;
+      for (int l = 2; l < kp; ++l) n2 += (P.lv[l].flags & kLvStore) ? 1 : 0;
+      P.n_store = n2;
+      hp.n_buffers = n2;
+      P.k = kp + 1;
+      P.leaf_choose = r | (ext << 8);
+      hp.choose_r = r;
+    }
+  }
   *out = hp;
   return GPM_OK;
 }

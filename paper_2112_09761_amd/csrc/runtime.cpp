@@ -1033,8 +1033,9 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
     qw.n_jobs += 1;
     return GPM_OK;
   }
+  // counting-only pruning of a twin suffix (edge-induced) unless decompose = 0
   HostPlan hp;
-  st = build_plan(p, mode, false, &hp, &err);
+  st = build_plan(p, mode, false, &hp, &err, c->opt_decompose != 0);
   if (st) return fail(c, st, err);
   const bool ren = c->opt_rename != 0;
   if (ren) {
@@ -2284,9 +2285,10 @@ gpm_status gpm_plan(const gpm_pattern* p, int mode, gpm_plan_info* out) {
   HostPlan hp;
   gpm_status st = validate_pattern(*p, nullptr);
   if (st) return st;
-  st = build_plan(*p, mode, is_clique(*p) && p->k >= 3, &hp, nullptr);
+  st = build_plan(*p, mode, is_clique(*p) && p->k >= 3, &hp, nullptr, true);
   if (st) return st;
   std::memset(out, 0, sizeof(*out));
+  out->count_only_r = hp.choose_r;
   out->k = hp.k;
   out->clique = hp.clique;
   out->aut = hp.aut;

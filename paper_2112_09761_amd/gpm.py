@@ -105,7 +105,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("clique", ctypes.c_int32), ("aut", ctypes.c_int32),
                 ("root_bound", ctypes.c_int32), ("n_buffers", ctypes.c_int32),
                 ("n_restrictions", ctypes.c_int32), ("order", ctypes.c_int32 * MAX_K),
-                ("restrictions", ctypes.c_int32 * (2 * MAX_PATTERN_EDGES))]
+                ("restrictions", ctypes.c_int32 * (2 * MAX_PATTERN_EDGES)),
+                ("count_only_r", ctypes.c_int32)]
 
 
 class GpmError(RuntimeError):
@@ -210,6 +211,7 @@ def plan(pattern, mode: int) -> dict:
         "order": list(info.order[:info.k]),
         "restrictions": [(info.restrictions[2 * i], info.restrictions[2 * i + 1])
                          for i in range(info.n_restrictions)],
+        "count_only_r": info.count_only_r,
     }
 
 

@@ -565,6 +565,70 @@ def test_serving_admission_waits_for_memory(oracle):
         assert e.value.status == -1
 
 
+def test_counting_only_pruning(ctx, oracle):
+    """Counting-only pruning of twin suffixes (Sec. 5.4 (1)): edge-induced
+    counts of patterns whose last r twins are chosen as C(n, r) from one
+    candidate set equal the plain DFS plan (decompose = 0), the oracle's
+    embeddings / |Aut|, and the closed forms on K_n."""
+    import math
+    book3 = (5, [(0, 1), (0, 2), (1, 2), (0, 3), (1, 3), (0, 4), (1, 4)])
+    k23 = (5, [(0, 2), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4)])
+    k24 = (6, [(0, 2), (0, 3), (0, 4), (0, 5), (1, 2), (1, 3), (1, 4), (1, 5)])
+    star4 = (5, [(0, 1), (0, 2), (0, 3), (0, 4)])
+    pendants = (5, [(0, 1), (1, 2), (0, 2), (0, 3), (0, 4)])
+    house_twins = (6, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (1, 4), (0, 5), (1, 5)])
+    pats = [book3, k23, k24, star4, pendants, house_twins]
+    for p in pats:
+        assert gpm_plan_r(p) >= 2, p
+    gs = [synth.erdos_renyi(60, 0.2, 1801), synth.rmat(8, 8, seed=1802),
+          synth.chung_lu(400, 6.0, 2.1, 60.0, 1200, 1803), synth.complete_multipartite([3, 4, 5])]
+    for g in gs:
+        gid = ctx.load(g)
+        try:
+            for p in pats:
+                exp = oracle.count_embed(g, p, False)
+                ctx.set_option("decompose", 0)
+                plain = ctx.count(gid, p, E)
+                ctx.set_option("decompose", 1)
+                got = ctx.count(gid, p, E)
+                assert got == plain == exp, (g.name, p, got, plain, exp)
+        finally:
+            ctx.set_option("decompose", 1)
+            ctx.unload(gid)
+    # closed forms: a spine edge and 3 of the other n - 2 vertices (book, K_{2,3})
+    kn = synth.complete(12)
+    gid = ctx.load(kn)
+    try:
+        assert ctx.count(gid, book3, E) == math.comb(12, 2) * math.comb(10, 3)
+        assert ctx.count(gid, k23, E) == math.comb(12, 2) * math.comb(10, 3)
+        assert ctx.count(gid, star4, E) == 12 * math.comb(11, 4)
+    finally:
+        ctx.unload(gid)
+    # larger leaf sets (C(n, r) far beyond 32 bits) on an R-MAT graph with
+    # hubs, against the closed forms: books = sum over edges of C(t_e, 3)
+    # (t_e from A^2 on the edges), 4-stars = sum over vertices of C(d, 4)
+    g = synth.rmat(12, 16, seed=1804)
+    A = np.zeros((g.n, g.n), dtype=np.float32)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    A[src, g.col] = 1.0
+    t = (A @ A)[src, g.col].astype(np.int64)          # exact: entries < 2^24
+    up = src < g.col
+    books = sum(math.comb(int(x), 3) for x in t[up])
+    stars = sum(math.comb(int(d), 4) for d in np.diff(g.row_ptr))
+    assert stars > 1 << 32
+    gid = ctx.load(g)
+    try:
+        assert ctx.count(gid, book3, E) == books
+        assert ctx.count(gid, star4, E) == stars
+    finally:
+        ctx.unload(gid)
+
+
+def gpm_plan_r(p):
+    from paper_2112_09761_amd import gpm
+    return gpm.plan(p, E)["count_only_r"]
+
+
 def test_edge_terms_fallback_with_large_roots(ctx, oracle):
     """Per-edge motif terms: with roots beyond the local-graph limit the
     triangle scatter cannot see every triangle, so the per-edge intersections

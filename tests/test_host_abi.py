@@ -113,6 +113,36 @@ def test_plan_properties(name, oracle):
             assert any((pl["order"][d], pl["order"][e]) in adj for e in range(d))
 
 
+def test_counting_only_suffix():
+    """Counting-only pruning (Sec. 5.4 (1)) in the count plan: the last r >= 2
+    vertices of the matching order are pairwise non-adjacent twins beside a
+    connected rest of >= 2 vertices, edge-induced mode only; the 4-cycle, the
+    paper's example of a pattern without the opportunity, has none."""
+    book3 = (5, [(0, 1), (0, 2), (1, 2), (0, 3), (1, 3), (0, 4), (1, 4)])
+    k23 = (5, [(0, 2), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4)])
+    k24 = (6, [(0, 2), (0, 3), (0, 4), (0, 5), (1, 2), (1, 3), (1, 4), (1, 5)])
+    star4 = (5, [(0, 1), (0, 2), (0, 3), (0, 4)])
+    pendants = (5, [(0, 1), (1, 2), (0, 2), (0, 3), (0, 4)])
+    expect = {"diamond": 2, "star3": 2, "cycle4": 0, "path4": 0, "tailed_triangle": 0,
+              "wedge": 0, "triangle": 0, "clique4": 0}
+    for name, r in expect.items():
+        assert gpm.plan(name, 1)["count_only_r"] == r, name
+        assert gpm.plan(name, 0)["count_only_r"] == 0, name
+    for pat, r in ((book3, 3), (k23, 2), (k24, 3), (star4, 3), (pendants, 2)):
+        pl = gpm.plan(pat, 1)
+        assert pl["count_only_r"] == r, pat
+        assert gpm.plan(pat, 0)["count_only_r"] == 0
+        # the twins close the order, each adjacent to an earlier vertex
+        k, edges = pat
+        adj = {(a, b) for a, b in edges} | {(b, a) for a, b in edges}
+        tail = pl["order"][k - r:]
+        for x in tail:
+            for y in tail:
+                assert (x, y) not in adj
+            assert {z for z in range(k) if (x, z) in adj} == \
+                {z for z in range(k) if (tail[0], z) in adj}
+
+
 def test_stabiliser_chain_count_identity(oracle):
     """The restrictions admit exactly one of the |Aut| automorphic images of
     every embedding: counting the embeddings of P into P itself that satisfy
