@@ -551,28 +551,44 @@ SERVE_PATTERNS = [("triangle", 0), ("clique4", 0), ("clique5", 0),
 
 def run_serve(args, ctx, torch):
     """Poisson stream of (graph, pattern) queries over a resident pool of 32
-    R-MAT graphs (scales 16..23), continuous batching, p50/p99 latency."""
+    R-MAT graphs (scales 16..23), continuous batching; per offered load 100
+    warm-up queries, then 1000 measured ones; p50/p99 latency overall and per
+    pattern; the served form against a plain one-query-at-a-time run of the
+    same stream."""
     import numpy as np
     from paper_2112_09761_amd import gpm
     n_pool = int(os.environ.get("GPM_SERVE_POOL", "32"))
-    n_q = int(os.environ.get("GPM_SERVE_QUERIES", "40"))
+    n_q = int(os.environ.get("GPM_SERVE_QUERIES", "1000"))
+    n_warm = int(os.environ.get("GPM_SERVE_WARMUP", "100"))
     t = time.perf_counter()
     graphs = gen_parallel(_gen_pool, n_pool)
     gen_s = time.perf_counter() - t
-    ids = []
+    ids, shas = [], []
     for i, (n, rp, col) in enumerate(graphs):
         ids.append(ctx.load_csr(rp, col))
         ctx.prepare(ids[-1])   # resident and prepared before any query
         progress(f"pool graph {i + 1}/{n_pool} loaded and prepared")
+    del graphs
     ctx.set_option("max_batch", int(os.environ.get("GPM_SERVE_MAX_BATCH", "8")))
     # every (graph, pattern) pair alone, warm: reference results and costs
     alone, cost = {}, {}
     for gi, gid in enumerate(ids):
         for pi, (name, mode) in enumerate(SERVE_PATTERNS):
+            ctx.count(gid, name, mode)
             t = time.perf_counter()
             alone[(gi, pi)] = ctx.count(gid, name, mode)
             cost[(gi, pi)] = time.perf_counter() - t
-            progress(f"alone graph {gi + 1}/{n_pool} {name}: {cost[(gi, pi)] * 1e3:.1f} ms")
+        progress(f"alone: graph {gi + 1}/{n_pool} done")
+    gold = golden("serve_pool")
+    oracle_checked = oracle_ok = 0
+    if gold:
+        by_i = {r["i"]: r for r in gold["graphs"]}
+        for (gi, pi), c in alone.items():
+            rec = by_i.get(gi, {}).get("counts", {})
+            name = SERVE_PATTERNS[pi][0]
+            if name in rec:
+                oracle_checked += 1
+                oracle_ok += int(rec[name] == c)
     rng = np.random.default_rng(20_000)
 
     def draw(n):
@@ -583,33 +599,63 @@ def run_serve(args, ctx, torch):
         name, mode = SERVE_PATTERNS[pi]
         return gpm.count_query(ids[gi], name, mode)
 
-    # saturated throughput: everything submitted at once
+    mix_ok = True
+
+    def closed_loop(qs, label):
+        """All queries submitted at once (as the slots and the pending list
+        take them); returns queries/s."""
+        nonlocal mix_ok
+        t0 = time.perf_counter()
+        pending = {}
+        nxt = 0
+        done_n = 0
+        while nxt < len(qs) or pending:
+            while nxt < len(qs):
+                try:
+                    pending[ctx.submit(query(*qs[nxt]))] = nxt
+                    nxt += 1
+                except gpm.GpmError as e:
+                    if e.status != -7:
+                        raise
+                    break
+            for tk in list(pending):
+                done, out = ctx.poll(tk)
+                if done:
+                    i = pending.pop(tk)
+                    mix_ok &= out[0] == alone[qs[i]]
+                    done_n += 1
+                    if done_n % 200 == 0:
+                        progress(f"{label}: {done_n}/{len(qs)} done")
+        return len(qs) / (time.perf_counter() - t0)
+
+    # saturated throughput mu (closed loop), then the plain form: the same
+    # stream one query at a time, each waiting for the previous one
     sat = draw(n_q)
-    t = time.perf_counter()
-    tickets = [ctx.submit(query(gi, pi)) for gi, pi in sat]
-    res = [None] * n_q
-    left = dict(zip(tickets, range(n_q)))
-    while left:
-        for tk in list(left):
-            done, out = ctx.poll(tk)
-            if done:
-                res[left.pop(tk)] = out[0]
-                progress(f"saturated: {n_q - len(left)}/{n_q} done")
-    mu = n_q / (time.perf_counter() - t)
-    mix_ok = all(r == alone[q] for r, q in zip(res, sat))
-    progress(f"saturated throughput {mu:.1f} queries/s, results identical: {mix_ok}")
+    mu = closed_loop(sat, "saturated")
+    progress(f"saturated throughput {mu:.1f} queries/s")
+    t0 = time.perf_counter()
+    for j, (gi, pi) in enumerate(sat):
+        name, mode = SERVE_PATTERNS[pi]
+        mix_ok &= ctx.count(ids[gi], name, mode) == alone[(gi, pi)]
+        if (j + 1) % 200 == 0:
+            progress(f"plain: {j + 1}/{n_q} done")
+    plain_qps = n_q / (time.perf_counter() - t0)
+    progress(f"plain throughput {plain_qps:.1f} queries/s")
     loads = []
     for frac in (0.3, 0.6, 0.9):
         lam = frac * mu
-        qs = draw(n_q)
-        arrive = np.cumsum(rng.exponential(1.0 / lam, size=n_q))
-        lat = [None] * n_q
+        total = n_warm + n_q
+        qs = draw(total)
+        arrive = np.cumsum(rng.exponential(1.0 / lam, size=total))
+        lat = [None] * total
         pending = {}
         t0 = time.perf_counter()
         nxt = 0
-        while nxt < n_q or pending:
+        finished = 0
+        t_first = t_last = None
+        while nxt < total or pending:
             now = time.perf_counter() - t0
-            while nxt < n_q and arrive[nxt] <= now:
+            while nxt < total and arrive[nxt] <= now:
                 gi, pi = qs[nxt]
                 pending[ctx.submit(query(gi, pi))] = nxt
                 nxt += 1
@@ -619,26 +665,42 @@ def run_serve(args, ctx, torch):
                     i = pending.pop(tk)
                     lat[i] = (time.perf_counter() - t0) - arrive[i]
                     mix_ok &= out[0] == alone[qs[i]]
-                    progress(f"load {frac}: {sum(x is not None for x in lat)}/{n_q} done")
-            if not pending and nxt < n_q:
+                    finished += 1
+                    if finished % 200 == 0:
+                        progress(f"load {frac}: {finished}/{total} done")
+            if not pending and nxt < total:
                 time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - t0), 0.001)))
-        span = time.perf_counter() - t0
-        la = np.array(lat) * 1e3
-        progress(f"load {frac}: {n_q / span:.1f} queries/s")
-        loads.append({"offered_qps": lam, "achieved_qps": n_q / span,
+        # measured window: the queries after the warm-up ones
+        meas = list(range(n_warm, total))
+        span = max(arrive[i] + lat[i] for i in meas) - arrive[n_warm]
+        la = np.array([lat[i] for i in meas]) * 1e3
+        per = {}
+        for pi, (name, _) in enumerate(SERVE_PATTERNS):
+            x = np.array([lat[i] for i in meas if qs[i][1] == pi]) * 1e3
+            if x.size:
+                per[name] = {"p50_ms": float(np.percentile(x, 50)),
+                             "p99_ms": float(np.percentile(x, 99)), "queries": int(x.size)}
+        achieved = n_q / span
+        progress(f"load {frac}: {achieved:.1f} queries/s, p50 {np.percentile(la, 50):.0f} ms, "
+                 f"p99 {np.percentile(la, 99):.0f} ms")
+        loads.append({"offered_qps": lam, "achieved_qps": achieved,
                       "p50_ms": float(np.percentile(la, 50)),
-                      "p99_ms": float(np.percentile(la, 99)), "queries": n_q})
+                      "p99_ms": float(np.percentile(la, 99)), "queries": n_q,
+                      "warmup_queries": n_warm, "per_pattern": per})
     per_pattern = {SERVE_PATTERNS[pi][0]: float(np.median([cost[(g, pi)] for g in range(n_pool)]) * 1e3)
                    for pi in range(len(SERVE_PATTERNS))}
     return {"metric": "served queries/s and p99 latency (Poisson stream, continuous batching)",
             "value": loads[-1]["achieved_qps"], "unit": "queries/s", "n_gpus": 1,
-            "steps": n_q, "warmup": 0, "ms_per_step": 1e3 / loads[-1]["achieved_qps"],
+            "steps": n_q, "warmup": n_warm, "ms_per_step": 1e3 / loads[-1]["achieved_qps"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "int32", "data": "synthetic",
             "config": {"workload": "serve_rmat_pool", "pool_graphs": n_pool,
                        "scales": sorted({16 + i // 4 for i in range(n_pool)}),
                        "patterns": [p for p, _ in SERVE_PATTERNS]},
-            "saturated_qps": mu, "loads": loads, "alone_vs_mix_identical": bool(mix_ok),
+            "saturated_qps": mu, "plain_qps": plain_qps, "served_vs_plain": mu / plain_qps,
+            "loads": loads, "alone_vs_mix_identical": bool(mix_ok),
+            "pairs_checked_against_stored_oracle": oracle_checked,
+            "pairs_equal_to_stored_oracle": oracle_ok,
             "median_alone_ms_by_pattern": per_pattern, "generation_s": gen_s}
 
 

@@ -542,15 +542,18 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
 }
 
 // 5-clique count of one local edge (i, j) of an ordered local graph with rows
-// of WC words: Σ_{l ∈ M} |M ∩ R_l|, M = R_i & R_j (bits above j only).
+// of W <= WC words (W == WC except in the wide instance, whose rows are
+// narrower than its register array): Σ_{l ∈ M} |M ∩ R_l|, M = R_i & R_j
+// (bits above j only).
 template <int WC>
-__device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32_t i, int32_t j) {
-  const unsigned long long* Ri = R + (size_t)i * WC;
-  const unsigned long long* Rj = R + (size_t)j * WC;
+__device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32_t i, int32_t j,
+                                              int32_t W) {
+  const unsigned long long* Ri = R + (size_t)i * W;
+  const unsigned long long* Rj = R + (size_t)j * W;
   const int jw = (j + 1) >> 6;
   uint64_t M[WC];
 #pragma unroll
-  for (int x = 0; x < WC; ++x) M[x] = (x >= jw) ? (Ri[x] & Rj[x]) : 0ull;
+  for (int x = 0; x < WC; ++x) M[x] = (x >= jw && x < W) ? (Ri[x] & Rj[x]) : 0ull;
   uint32_t cp = 0;
 #pragma unroll
   for (int x = 0; x < WC; ++x) {
@@ -561,9 +564,10 @@ __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32
         int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
         m &= m - 1u;
         asm volatile("" : "+v"(lrow));
-        const unsigned long long* Rl = R + __umul24((uint32_t)lrow, (uint32_t)WC);
+        const unsigned long long* Rl = R + __umul24((uint32_t)lrow, (uint32_t)W);
 #pragma unroll
-        for (int y = x; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
+        for (int y = x; y < WC; ++y)
+          if (y < W) cp += (uint32_t)__popcll(M[y] & Rl[y]);
       }
     }
   }
@@ -580,8 +584,8 @@ __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32
 template <int WC>
 __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
                                                       const unsigned long long* R, int32_t d,
-                                                      int32_t p0, int32_t p1, int32_t* ids,
-                                                      int32_t* cnt) {
+                                                      int32_t W, int32_t p0, int32_t p1,
+                                                      int32_t* ids, int32_t* cnt) {
   constexpr int K = kSortBatch / 64;
   const int l = lane_id();
   const int wv = threadIdx.x >> 6;
@@ -598,7 +602,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
       if (t < p1) {
         const int32_t i = upper_bound(P + 1, d, t);
         int32_t r = t - P[i];
-        const unsigned long long* Ri = R + (size_t)i * WC;
+        const unsigned long long* Ri = R + (size_t)i * W;
         int32_t w = 0;
         for (;; ++w) {
           const int32_t pc = __popcll(Ri[w]);
@@ -606,13 +610,13 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
           r -= pc;
         }
         const int32_t j = w * 64 + select64(Ri[w], r);
-        const unsigned long long* Rj = R + (size_t)j * WC;
+        const unsigned long long* Rj = R + (size_t)j * W;
         const int jw = (j + 1) >> 6;
         int32_t m = 0;
 #pragma unroll
         for (int x = 0; x < WC; ++x)
-          if (x >= jw) m += __popcll(Ri[x] & Rj[x]);
-        const int32_t v = min(m * (WC - jw), 65535);
+          if (x >= jw && x < W) m += __popcll(Ri[x] & Rj[x]);
+        const int32_t v = min(m * (W - jw), 65535);
         key[q] = v < 4 ? v : ((31 - __clz(v)) << 2) | ((v >> (29 - __clz(v))) & 3);
         pid[q] = (i << 16) | j;
         atomicAdd(&cnt[key[q]], 1);
@@ -634,7 +638,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
       const int32_t idx = q * 64 + l;
       if (idx < nvalid) {
         const int32_t e = ids[idx];
-        c += lgs_edge5<WC>(R, e >> 16, e & 0xffff);
+        c += lgs_edge5<WC>(R, e >> 16, e & 0xffff, W);
       }
     }
     wave_sync_mem();  // the next batch reuses ids and cnt
@@ -798,15 +802,18 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* tmp, int3
 }
 
 // The same local-graph search as clique_lgs, for a root u with
-// d <= kLgsBlockMaxVertices out-neighbours, with every step spread over the
-// workgroup (rows dealt round-robin to its waves) and the tile (T = d) in
-// its LDS.  Every thread returns its partial count.
-template <bool CE>
+// d <= kLgsMaxVertices out-neighbours, with every step spread over the
+// workgroup (rows taken by its waves from an LDS counter, per-vertex steps
+// two vertices per thread above 1024) and the tile (T = d) in its LDS; with
+// Rg the bitmap rows are in that HBM region instead (local graphs whose rows
+// do not fit the LDS: L, P and the hash stay in it).  Every thread returns
+// its partial count.
+template <bool CE, bool HBM>
 __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__ rp,
                                      const int32_t* __restrict__ col, int k, int32_t u,
                                      int32_t d, int32_t part, int32_t parts, bool ordered,
                                      int32_t* lds, int32_t* tmp, int32_t* next, int32_t* sort_area,
-                                     unsigned int* tri, ElemCounter& ec) {
+                                     unsigned int* tri, unsigned long long* Rg, ElemCounter& ec) {
   constexpr int NT = kBlockWaves * 64;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
@@ -815,19 +822,15 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   int32_t* L = lds;
   int32_t* P = lds + d;
   unsigned long long* H = (unsigned long long*)(lds + lgs_hash_offset(d));
-  unsigned long long* R = (unsigned long long*)(lds + lgs_rows_offset(d));
+  unsigned long long* R = HBM ? Rg : (unsigned long long*)(lds + lgs_rows_offset(d));
   const int32_t* Nu = col + rp[u];
   for (int32_t i = tid; i < (1 << bits); i += NT) H[i] = 0ull;
   if (k > 3)
     for (int32_t i = tid; i < d * W; i += NT) R[i] = 0ull;
-  int32_t v = 0;
-  if (tid < d) {
-    v = Nu[tid];
-    L[tid] = v;
-  }
+  for (int32_t i = tid; i < d; i += NT) L[i] = Nu[i];
   if (tid == 0) *next = 0;
   __syncthreads();
-  if (tid < d) lgs_hash_put(H, bits, v, tid);
+  for (int32_t i = tid; i < d; i += NT) lgs_hash_put(H, bits, L[i], i);
   __syncthreads();
   if (CE && tid < 64) {
     ec.elems += (uint64_t)d * (uint64_t)d;
@@ -853,12 +856,24 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   __syncthreads();
   uint64_t c = 0;
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
-  int32_t pc = 0;
-  if (tid < d)
-    for (int32_t w = 0; w < W; ++w) pc += __popcll(R[(size_t)tid * W + w]);
+  // (thread t holds rows t * rpt .. t * rpt + rpt - 1)
+  const int32_t rpt = (d + NT - 1) / NT;
+  int32_t pcr[2] = {0, 0};
+  for (int32_t q = 0; q < rpt; ++q) {
+    const int32_t i = tid * rpt + q;
+    if (i < d)
+      for (int32_t w = 0; w < W; ++w) pcr[q] += __popcll(R[(size_t)i * W + w]);
+  }
   int32_t pairs = 0;
-  const int32_t inc2 = block_incl_scan(pc, tmp, pairs);
-  if (tid < d) P[tid + 1] = inc2;
+  const int32_t inc2 = block_incl_scan(pcr[0] + pcr[1], tmp, pairs);
+  {
+    int32_t run = inc2 - pcr[0] - pcr[1];
+    for (int32_t q = 0; q < rpt; ++q) {
+      const int32_t i = tid * rpt + q;
+      run += pcr[q];
+      if (i < d) P[i + 1] = run;
+    }
+  }
   if (tid == 0) P[0] = 0;
   __syncthreads();
   const int32_t p0 = (int32_t)((int64_t)pairs * part / parts);
@@ -887,15 +902,22 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   if (!CE && ordered) {
     int32_t* ids = sort_area + (size_t)wv * kSortWords;
     int32_t* bcnt = ids + kSortBatch;
+    // rows in HBM (local graphs above the LDS tile): one wide instance for
+    // every width up to kLgsMaxVertices / 64 words
+    if constexpr (HBM) {
+      if (W <= kLgsMaxVertices / 64)
+        return lgs_pairs5_sorted<kLgsMaxVertices / 64>(P, R, d, W, p0, p1, ids, bcnt);
+    } else {
     switch (W) {
 #define GPM_LGSB5(WC) \
   case WC:            \
-    return lgs_pairs5_sorted<WC>(P, R, d, p0, p1, ids, bcnt);
+    return lgs_pairs5_sorted<WC>(P, R, d, WC, p0, p1, ids, bcnt);
       GPM_LGSB5(1) GPM_LGSB5(2) GPM_LGSB5(3) GPM_LGSB5(4) GPM_LGSB5(5) GPM_LGSB5(6)
       GPM_LGSB5(7) GPM_LGSB5(8) GPM_LGSB5(9) GPM_LGSB5(10) GPM_LGSB5(11) GPM_LGSB5(12)
       GPM_LGSB5(13) GPM_LGSB5(14) GPM_LGSB5(15) GPM_LGSB5(16)
 #undef GPM_LGSB5
       default: break;
+    }
     }
   }
   // instrumented or unordered: words recomputed
@@ -1958,9 +1980,20 @@ gpm_lgs_block(KernelArgs a) {
         parts = enc >> 16;
       }
       // the edge-sorting area follows the largest tile of the launch
-      acc[0] += clique_lgs_block<CE>(J.rp, J.col, J.k, u, d, part, parts, J.ordered != 0,
-                                     blk_lds, scan_tmp, &row_next,
-                                     blk_lds + a.lds_words - kBlockWaves * kSortWords, J.tri, ec);
+      // rows in the workgroup's HBM region when the job's local graphs exceed the LDS
+      unsigned long long* Rg =
+          J.lds_ok ? nullptr
+                   : (unsigned long long*)(a.fbuf + (int64_t)blockIdx.x * a.wave_stride);
+      if (Rg)
+        acc[0] += clique_lgs_block<CE, true>(J.rp, J.col, J.k, u, d, part, parts,
+                                             J.ordered != 0, blk_lds, scan_tmp, &row_next,
+                                             blk_lds + a.lds_words - kBlockWaves * kSortWords,
+                                             J.tri, Rg, ec);
+      else
+        acc[0] += clique_lgs_block<CE, false>(J.rp, J.col, J.k, u, d, part, parts,
+                                              J.ordered != 0, blk_lds, scan_tmp, &row_next,
+                                              blk_lds + a.lds_words - kBlockWaves * kSortWords,
+                                              J.tri, nullptr, ec);
       __syncthreads();  // the next root reuses the local graph's LDS
     }
   }

@@ -928,8 +928,9 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
       int64_t hi = std::upper_bound(dg.begin(), dg.end(), (int64_t)(p.k - 1),
                                     [](int64_t x, int64_t y) { return x > y; }) - dg.begin();
       // [lo, hi) splits by out-degree d into [lo, b0): d above the workgroup
-      // limit (per wave, rows in HBM); [b0, mid): above the per-wave LDS tile,
-      // one workgroup per root; [mid, hi): per wave, rows in LDS
+      // LDS tile (one workgroup per root, bitmap rows in its HBM region);
+      // [b0, mid): above the per-wave LDS tile, one workgroup per root with
+      // the tile in its LDS; [mid, hi): per wave, rows in LDS
       int64_t b0 = lo, mid = lo;
       if (c->opt_lgs_block && hi > lo) {
         auto first_at_most = [&](int64_t v) {
@@ -940,10 +941,11 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
         b0 = std::min(first_at_most(lgs_block_max_vertices(c)), mid);
       }
       auto add_lgs = [&](int kind, int64_t a, int64_t b, int which, int64_t units,
-                         bool split, bool always) -> gpm_status {
+                         bool split, bool always, int lds_rows) -> gpm_status {
         if (b <= a && !always) return GPM_OK;
         Job L = J;
         L.kind = kind;
+        L.lds_ok = lds_rows;
         L.vertex_tasks = 1;
         L.task_src = g.lgs_vtx + a;
         L.task_dst = nullptr;
@@ -960,16 +962,22 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
         // largest root of the range (heaviest first)
         L.cap = (int32_t)(b > a ? dg[a] : std::min<int64_t>(cap, c->opt_lgs_max));
         js.jobs.push_back(L);
-        js.need_words.push_back(0);  // sized at launch from the LDS tile
+        // workgroup roots with rows in HBM: one region of the rows per workgroup
+        js.need_words.push_back(kind == kJobCliqueLgsBlock && !lds_rows
+                                    ? 2 * (int64_t)L.cap * (((int64_t)L.cap + 63) / 64)
+                                    : 0);
         qw.n_jobs += 1;
         return GPM_OK;
       };
       const int64_t waves = (int64_t)c->cus * 16;
-      st = add_lgs(kJobCliqueLgs, mid, hi, 0, waves, p.k >= 5, true);
+      st = add_lgs(kJobCliqueLgs, mid, hi, 0, waves, p.k >= 5, true, 1);
       if (st) return st;
-      st = add_lgs(kJobCliqueLgsBlock, b0, mid, 1, (int64_t)c->cus, p.k >= 4, false);
+      st = add_lgs(kJobCliqueLgsBlock, b0, mid, 1, (int64_t)c->cus, p.k >= 4, false, 1);
       if (st) return st;
-      st = add_lgs(kJobCliqueLgs, lo, b0, 2, waves, p.k >= 5, false);
+      if (c->opt_lgs_block)
+        st = add_lgs(kJobCliqueLgsBlock, lo, b0, 2, (int64_t)c->cus, p.k >= 4, false, 0);
+      else
+        st = add_lgs(kJobCliqueLgs, lo, b0, 2, waves, p.k >= 5, false, 1);
       if (st) return st;
       if (g.n_big) {
         Job B = J;
@@ -1458,12 +1466,19 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     }
   if (lgs_T) lds_words = std::max<int32_t>(lds_words, (int32_t)align_up((size_t)lgs_tile_words(lgs_T), 4));
   // workgroup kernel: room for the largest root of its jobs
-  int64_t blk_cap = 0;
+  // (jobs with rows in HBM keep only L, P and the hash in LDS)
+  int64_t blk_tile = 0, blk_vmax = 0;
+  bool blk_hbm_rows = false;
   for (int i = 0; i < nj; ++i)
-    if (jobs[i].kind == kJobCliqueLgsBlock) blk_cap = std::max<int64_t>(blk_cap, jobs[i].cap);
+    if (jobs[i].kind == kJobCliqueLgsBlock) {
+      const int64_t t = jobs[i].lds_ok ? lgs_tile_words(jobs[i].cap) : lgs_rows_offset(jobs[i].cap);
+      blk_tile = std::max(blk_tile, t);
+      blk_vmax = std::max<int64_t>(blk_vmax, jobs[i].cap);
+      if (!jobs[i].lds_ok) blk_hbm_rows = true;
+    }
   const size_t blk_lds =
-      blk_cap ? ((size_t)align_up((size_t)lgs_tile_words(blk_cap), 4) + kBlockSortWords) * 4 : 0;
-  if (blk_cap && (blk_cap > kLgsBlockMaxVertices || blk_lds + 256 > (size_t)c->lds_block_max))
+      blk_tile ? ((size_t)align_up((size_t)blk_tile, 4) + kBlockSortWords) * 4 : 0;
+  if (blk_tile && (blk_vmax > kLgsMaxVertices || blk_lds + 256 > (size_t)c->lds_block_max))
     return fail(c, GPM_E_DEVICE, "local graph exceeds the workgroup LDS");
 
   // frontier sizing (adaptive buffering): one region of `stride` words per wave
@@ -1649,7 +1664,9 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     int e;
     if (L.kinds == kKindCliqueLgsBlock) {
       a.lds_words = (int32_t)(blk_lds / 4);
-      e = launch_lgs_block(c->opt_count_elements != 0, a, c->cus, L.chunks, blk_lds, s.stream);
+      // with rows in HBM each workgroup owns one frontier region
+      const int64_t max_blocks = blk_hbm_rows ? std::min<int64_t>(L.chunks, waves) : L.chunks;
+      e = launch_lgs_block(c->opt_count_elements != 0, a, c->cus, max_blocks, blk_lds, s.stream);
     } else if (L.kinds == kKindCycleBlock) {
       e = launch_cycle_block(c->opt_count_elements != 0, a,
                              (int)std::min<int64_t>(cyc_blocks, L.chunks), s.stream);
