@@ -570,11 +570,11 @@ def run_serve(args, ctx, torch):
         progress(f"pool graph {i + 1}/{n_pool} loaded and prepared")
     del graphs
     ctx.set_option("max_batch", int(os.environ.get("GPM_SERVE_MAX_BATCH", "8")))
-    # every (graph, pattern) pair alone, warm: reference results and costs
+    # every (graph, pattern) pair alone (the graphs are prepared): reference
+    # results and costs
     alone, cost = {}, {}
     for gi, gid in enumerate(ids):
         for pi, (name, mode) in enumerate(SERVE_PATTERNS):
-            ctx.count(gid, name, mode)
             t = time.perf_counter()
             alone[(gi, pi)] = ctx.count(gid, name, mode)
             cost[(gi, pi)] = time.perf_counter() - t
@@ -600,11 +600,21 @@ def run_serve(args, ctx, torch):
         return gpm.count_query(ids[gi], name, mode)
 
     mix_ok = True
+    mismatches = []
+
+    def check(phase, pair, got):
+        nonlocal mix_ok
+        if got != alone[pair]:
+            mix_ok = False
+            if len(mismatches) < 20:
+                mismatches.append({"phase": phase, "graph": pair[0],
+                                   "pattern": SERVE_PATTERNS[pair[1]][0], "got": got,
+                                   "alone": alone[pair]})
+                progress(f"MISMATCH {mismatches[-1]}")
 
     def closed_loop(qs, label):
         """All queries submitted at once (as the slots and the pending list
         take them); returns queries/s."""
-        nonlocal mix_ok
         t0 = time.perf_counter()
         pending = {}
         nxt = 0
@@ -622,7 +632,7 @@ def run_serve(args, ctx, torch):
                 done, out = ctx.poll(tk)
                 if done:
                     i = pending.pop(tk)
-                    mix_ok &= out[0] == alone[qs[i]]
+                    check(label, qs[i], out[0])
                     done_n += 1
                     if done_n % 200 == 0:
                         progress(f"{label}: {done_n}/{len(qs)} done")
@@ -636,7 +646,7 @@ def run_serve(args, ctx, torch):
     t0 = time.perf_counter()
     for j, (gi, pi) in enumerate(sat):
         name, mode = SERVE_PATTERNS[pi]
-        mix_ok &= ctx.count(ids[gi], name, mode) == alone[(gi, pi)]
+        check("plain", (gi, pi), ctx.count(ids[gi], name, mode))
         if (j + 1) % 200 == 0:
             progress(f"plain: {j + 1}/{n_q} done")
     plain_qps = n_q / (time.perf_counter() - t0)
@@ -664,7 +674,7 @@ def run_serve(args, ctx, torch):
                 if done:
                     i = pending.pop(tk)
                     lat[i] = (time.perf_counter() - t0) - arrive[i]
-                    mix_ok &= out[0] == alone[qs[i]]
+                    check(f"load {frac}", qs[i], out[0])
                     finished += 1
                     if finished % 200 == 0:
                         progress(f"load {frac}: {finished}/{total} done")
@@ -698,7 +708,7 @@ def run_serve(args, ctx, torch):
                        "scales": sorted({16 + i // 4 for i in range(n_pool)}),
                        "patterns": [p for p, _ in SERVE_PATTERNS]},
             "saturated_qps": mu, "plain_qps": plain_qps, "served_vs_plain": mu / plain_qps,
-            "loads": loads, "alone_vs_mix_identical": bool(mix_ok),
+            "loads": loads, "alone_vs_mix_identical": bool(mix_ok), "mismatches": mismatches,
             "pairs_checked_against_stored_oracle": oracle_checked,
             "pairs_equal_to_stored_oracle": oracle_ok,
             "median_alone_ms_by_pattern": per_pattern, "generation_s": gen_s}

@@ -2295,6 +2295,10 @@ __device__ __forceinline__ void cyc_ranges(const int64_t* __restrict__ rp,
         cursor[3 * i] = cursor[3 * i + 2];
       __syncthreads();
     }
+    // every wave has seen the empty stack before thread 0 sets up the next
+    // range (else a late wave would read the new entry and fall one barrier
+    // out of step with the others)
+    __syncthreads();
   }
 }
 
@@ -2415,6 +2419,8 @@ __device__ __forceinline__ void cyc_hash_task(const int64_t* __restrict__ rp,
     }
     __syncthreads();
   }
+  // every wave has seen the empty stack before the shared state is reused
+  __syncthreads();
 }
 
 // Persistent workgroup kernel of the 4-cycle tasks: wave 0 pops a chunk of

@@ -515,21 +515,21 @@ def test_serving_admission_waits_for_memory(oracle):
     with gpm.Context(0, torch.cuda.current_stream()) as c0:
         gid = c0.load(g)
         dmax = c0.graph_info(gid)["max_degree"]
-    x = gpm.plan("diamond", E)["n_buffers"]
+    x = gpm.plan("diamond", V)["n_buffers"]   # the DFS plan stores one level
     assert x >= 1
     stride = -(-x * dmax // 64) * 64            # frontier words per wave
     min_bytes = stride * 4 * cus                # one wave per CU
-    exp_big = oracle.count(g, "diamond", False)
-    exp_small = oracle.count(small, "diamond", False)
+    exp_big = oracle.count(g, "diamond", True)
+    exp_small = oracle.count(small, "diamond", True)
     with gpm.Context(0, torch.cuda.current_stream(), budget=min_bytes * 3 // 2) as c:
         c.set_option("decompose", 0)            # the DFS plan: it needs frontier memory
         ids = [c.load(g), c.load(small)]
         t_alone = time.perf_counter()
-        assert c.count(ids[0], "diamond", E) == exp_big
+        assert c.count(ids[0], "diamond", V) == exp_big
         t_alone = time.perf_counter() - t_alone
         st0 = c.serve_state()
-        t1 = c.submit(gpm.count_query(ids[0], "diamond", E))
-        t2 = c.submit(gpm.count_query(ids[1], "diamond", E))
+        t1 = c.submit(gpm.count_query(ids[0], "diamond", V))
+        t2 = c.submit(gpm.count_query(ids[1], "diamond", V))
         st = c.serve_state()
         # the first launch holds more than half the budget, so the second
         # query cannot start beside it
@@ -551,7 +551,7 @@ def test_serving_admission_waits_for_memory(oracle):
         assert e.value.status == -1
         # a budget below one wave per CU: the query completes with NOMEM
         c.set_option("budget", min_bytes // 4)
-        t3 = c.submit(gpm.count_query(ids[0], "diamond", E))
+        t3 = c.submit(gpm.count_query(ids[0], "diamond", V))
         with pytest.raises(gpm.GpmError) as e:
             c.wait(t3)
         assert e.value.status == -4
