@@ -31,8 +31,8 @@ WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
 # for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
 # the kernel sources they were taken on (and that launch) only; else null.
-TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856ae6169957da11ce16fb",
-           "k": 5, "kinds": 1 << 7, "fetch_kib": 1847122.3, "write_kib": 866.2,
+TRAFFIC = {"sources_sha256": "86f576b7179e56f5a840a2cd0da0f4198aa413e12de50eb2d4e84fbb43c1af80",
+           "k": 5, "kinds": 1 << 7, "fetch_kib": 1904233.9, "write_kib": 3938.2,
            "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
 
@@ -90,7 +90,8 @@ def measured_traffic(k, kinds):
 
 
 # gpm_list on the listing workload: the same two counter passes (KiB per
-# dispatch), valid for the sources they were taken on
+# dispatch), valid for the sources they were taken on (earlier sources than
+# the current ones: reported as null until taken again)
 LIST_TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856ae6169957da11ce16fb",
                 "fetch_kib": 160388.1, "write_kib": 5050520.3,
                 "fetch_factor": 2.0, "write_factor": 1.0}
@@ -98,7 +99,8 @@ LIST_TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856
 
 # gpm_cycle_block (4-cycles) on the Chung-Lu workload: the same two counter
 # passes (KiB per dispatch), valid for the sources they were taken on
-CYC_TRAFFIC = {"sources_sha256": "", "fetch_kib": 0.0, "write_kib": 0.0,
+CYC_TRAFFIC = {"sources_sha256": "86f576b7179e56f5a840a2cd0da0f4198aa413e12de50eb2d4e84fbb43c1af80",
+               "fetch_kib": 128875918.8, "write_kib": 19540046.4,
                "fetch_factor": 2.0, "write_factor": 1.0}
 
 
@@ -395,7 +397,9 @@ def run_list(args, ctx, torch):
                        "rows": n, "row_bytes": 16},
             "parity_vs_stored_oracle": parity, "kernel_ms": launch_ms,
             "count_kernel_ms": statistics.mean(cms),
-            "roofline": {"bound": "hbm", "kernel": "gpm_list (plan-driven walk, rows staged in LDS)",
+            "roofline": {"bound": "hbm", "limiter": "latency of the leaf's dependent loads "
+                                                    "(the HBM fraction is low by that, not by bytes)",
+                         "kernel": "gpm_list (plan-driven walk, rows staged in LDS)",
                          "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS,
                          "traffic": measured_list_traffic(),
