@@ -195,7 +195,20 @@ __host__ __device__ inline int64_t lgs_tile_words(int64_t T) {
   return lgs_rows_offset(T) + 2 * T * ((T + 63) / 64);
 }
 
-// The workgroup kernel lays out a root of d vertices as a tile with T = d.
+// The workgroup kernel lays out a root of d vertices as a tile with T = d,
+// its bitmap rows padded: a row of W words takes an odd number of words
+// (W | 1) where the tile then still fits within that of the largest root,
+// W <= kLgsPadWords.  The 64 lanes of a wave read 64 different rows at once;
+// with a stride of 2^a * b words (b odd) their first words fall on 2^-a as
+// many LDS banks as with an odd stride, so an even stride multiplies the bank
+// conflicts of those reads.
+constexpr int kLgsPadWords = 13;
+__host__ __device__ constexpr int64_t lgs_block_stride_words(int64_t W) {
+  return W <= kLgsPadWords ? (W | 1) : W;
+}
+__host__ __device__ inline int64_t lgs_block_tile_words(int64_t T) {
+  return lgs_rows_offset(T) + 2 * T * lgs_block_stride_words((T + 63) / 64);
+}
 
 // One listing launch (Sec. 2.1: listing enumerates every match instead of
 // counting it): the plan-driven walk of one pattern over one graph view,

@@ -543,13 +543,13 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
 
 // 5-clique count of one local edge (i, j) of an ordered local graph with rows
 // of W <= WC words (W == WC except in the wide instance, whose rows are
-// narrower than its register array): Σ_{l ∈ M} |M ∩ R_l|, M = R_i & R_j
-// (bits above j only).
+// narrower than its register array) at a stride of S >= W words:
+// Σ_{l ∈ M} |M ∩ R_l|, M = R_i & R_j (bits above j only).
 template <int WC>
 __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32_t i, int32_t j,
-                                              int32_t W) {
-  const unsigned long long* Ri = R + (size_t)i * W;
-  const unsigned long long* Rj = R + (size_t)j * W;
+                                              int32_t W, int32_t S) {
+  const unsigned long long* Ri = R + (size_t)i * S;
+  const unsigned long long* Rj = R + (size_t)j * S;
   const int jw = (j + 1) >> 6;
   uint64_t M[WC];
 #pragma unroll
@@ -564,7 +564,7 @@ __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32
         int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
         m &= m - 1u;
         asm volatile("" : "+v"(lrow));
-        const unsigned long long* Rl = R + __umul24((uint32_t)lrow, (uint32_t)W);
+        const unsigned long long* Rl = R + __umul24((uint32_t)lrow, (uint32_t)S);
 #pragma unroll
         for (int y = x; y < WC; ++y)
           if (y < W) cp += (uint32_t)__popcll(M[y] & Rl[y]);
@@ -580,12 +580,13 @@ __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32
 // logarithm of its cost estimate |R_i & R_j| · (words from j's on) — four
 // keys per octave, 0..63 — counting-sorts the batch by key in its LDS area
 // (ids, cnt), then counts the sorted edges 64 at a time, so that the lanes of
-// a round hold edges of similar cost.  Returns this thread's partial count.
+// a round hold edges of similar cost (rows of W words at a stride of S).
+// Returns this thread's partial count.
 template <int WC>
 __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
                                                       const unsigned long long* R, int32_t d,
-                                                      int32_t W, int32_t p0, int32_t p1,
-                                                      int32_t* ids, int32_t* cnt) {
+                                                      int32_t W, int32_t S, int32_t p0,
+                                                      int32_t p1, int32_t* ids, int32_t* cnt) {
   constexpr int K = kSortBatch / 64;
   const int l = lane_id();
   const int wv = threadIdx.x >> 6;
@@ -602,7 +603,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
       if (t < p1) {
         const int32_t i = upper_bound(P + 1, d, t);
         int32_t r = t - P[i];
-        const unsigned long long* Ri = R + (size_t)i * W;
+        const unsigned long long* Ri = R + (size_t)i * S;
         int32_t w = 0;
         for (;; ++w) {
           const int32_t pc = __popcll(Ri[w]);
@@ -610,7 +611,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
           r -= pc;
         }
         const int32_t j = w * 64 + select64(Ri[w], r);
-        const unsigned long long* Rj = R + (size_t)j * W;
+        const unsigned long long* Rj = R + (size_t)j * S;
         const int jw = (j + 1) >> 6;
         int32_t m = 0;
 #pragma unroll
@@ -638,7 +639,7 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
       const int32_t idx = q * 64 + l;
       if (idx < nvalid) {
         const int32_t e = ids[idx];
-        c += lgs_edge5<WC>(R, e >> 16, e & 0xffff, W);
+        c += lgs_edge5<WC>(R, e >> 16, e & 0xffff, W, S);
       }
     }
     wave_sync_mem();  // the next batch reuses ids and cnt
@@ -818,6 +819,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
   const int32_t W = (d + 63) >> 6;
+  const int32_t S = HBM ? W : (int32_t)lgs_block_stride_words(W);  // row stride
   const int32_t bits = lgs_hash_bits(d);
   int32_t* L = lds;
   int32_t* P = lds + d;
@@ -826,7 +828,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   const int32_t* Nu = col + rp[u];
   for (int32_t i = tid; i < (1 << bits); i += NT) H[i] = 0ull;
   if (k > 3)
-    for (int32_t i = tid; i < d * W; i += NT) R[i] = 0ull;
+    for (int32_t i = tid; i < d * S; i += NT) R[i] = 0ull;
   for (int32_t i = tid; i < d; i += NT) L[i] = Nu[i];
   if (tid == 0) *next = 0;
   __syncthreads();
@@ -852,7 +854,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
       if (P[i]) atomicAdd(&tri[e0 + i], (unsigned int)P[i]);
     return 0;
   }
-  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next);
+  lgs_build_rows<CE, true>(rp, col, L, d, S, H, bits, R, wv, kBlockWaves, ec, next);
   __syncthreads();
   uint64_t c = 0;
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
@@ -862,7 +864,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   for (int32_t q = 0; q < rpt; ++q) {
     const int32_t i = tid * rpt + q;
     if (i < d)
-      for (int32_t w = 0; w < W; ++w) pcr[q] += __popcll(R[(size_t)i * W + w]);
+      for (int32_t w = 0; w < W; ++w) pcr[q] += __popcll(R[(size_t)i * S + w]);
   }
   int32_t pairs = 0;
   const int32_t inc2 = block_incl_scan(pcr[0] + pcr[1], tmp, pairs);
@@ -882,7 +884,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
     for (int32_t t = p0 + tid; t < p1; t += NT) {
       const int32_t i = upper_bound(P + 1, d, t);
       int32_t r = t - P[i];
-      const unsigned long long* Ri = R + (size_t)i * W;
+      const unsigned long long* Ri = R + (size_t)i * S;
       int32_t w = 0;
       for (;; ++w) {
         const int32_t q = __popcll(Ri[w]);
@@ -890,7 +892,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
         r -= q;
       }
       const int32_t j = w * 64 + select64(Ri[w], r);
-      const unsigned long long* Rj = R + (size_t)j * W;
+      const unsigned long long* Rj = R + (size_t)j * S;
       const int32_t x0 = ordered ? ((j + 1) >> 6) : 0;
       uint32_t cp = 0;
       for (int32_t x = x0; x < W; ++x) cp += (uint32_t)__popcll(Ri[x] & Rj[x]);
@@ -906,12 +908,13 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
     // every width up to kLgsMaxVertices / 64 words
     if constexpr (HBM) {
       if (W <= kLgsMaxVertices / 64)
-        return lgs_pairs5_sorted<kLgsMaxVertices / 64>(P, R, d, W, p0, p1, ids, bcnt);
+        return lgs_pairs5_sorted<kLgsMaxVertices / 64>(P, R, d, W, W, p0, p1, ids, bcnt);
     } else {
     switch (W) {
 #define GPM_LGSB5(WC) \
   case WC:            \
-    return lgs_pairs5_sorted<WC>(P, R, d, WC, p0, p1, ids, bcnt);
+    return lgs_pairs5_sorted<WC>(P, R, d, WC, (int32_t)lgs_block_stride_words(WC), p0, p1, \
+                                  ids, bcnt);
       GPM_LGSB5(1) GPM_LGSB5(2) GPM_LGSB5(3) GPM_LGSB5(4) GPM_LGSB5(5) GPM_LGSB5(6)
       GPM_LGSB5(7) GPM_LGSB5(8) GPM_LGSB5(9) GPM_LGSB5(10) GPM_LGSB5(11) GPM_LGSB5(12)
       GPM_LGSB5(13) GPM_LGSB5(14) GPM_LGSB5(15) GPM_LGSB5(16)
@@ -924,7 +927,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   for (int32_t t = p0 + tid; t < p1; t += NT) {
     const int32_t i = upper_bound(P + 1, d, t);
     int32_t r = t - P[i];
-    const unsigned long long* Ri = R + (size_t)i * W;
+    const unsigned long long* Ri = R + (size_t)i * S;
     int32_t w = 0;
     for (;; ++w) {
       const int32_t q = __popcll(Ri[w]);
@@ -932,7 +935,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
       r -= q;
     }
     const int32_t j = w * 64 + select64(Ri[w], r);
-    const unsigned long long* Rj = R + (size_t)j * W;
+    const unsigned long long* Rj = R + (size_t)j * S;
     const int32_t jw = ordered ? ((j + 1) >> 6) : 0;
     if (CE) ec.words += (uint64_t)(W - jw);
     for (int32_t x = jw; x < W; ++x) {
@@ -940,7 +943,7 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
       while (m) {
         const int b = __builtin_ctzll(m);
         m &= m - 1ull;
-        const unsigned long long* Rl = R + (size_t)(x * 64 + b) * W;
+        const unsigned long long* Rl = R + (size_t)(x * 64 + b) * S;
         const int32_t y0 = ordered ? x : 0;
         for (int32_t y = y0; y < W; ++y) c += (uint64_t)__popcll(Ri[y] & Rj[y] & Rl[y]);
         if (CE) ec.words += (uint64_t)(W - y0);

@@ -726,7 +726,7 @@ static int default_chunk(const gpm_ctx* c, int kind) {
 // scans, and its tile (plus the kernel's static LDS) within the workgroup's LDS.
 static int64_t lgs_block_max_vertices(const gpm_ctx* c) {
   int64_t d = kLgsBlockMaxVertices;
-  while (d > 0 && (((lgs_tile_words(d) + 3) & ~int64_t(3)) + kBlockSortWords) * 4 + 256 >
+  while (d > 0 && (((lgs_block_tile_words(d) + 3) & ~int64_t(3)) + kBlockSortWords) * 4 + 256 >
                       (int64_t)c->lds_block_max)
     --d;
   return d;
@@ -1471,7 +1471,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
   bool blk_hbm_rows = false;
   for (int i = 0; i < nj; ++i)
     if (jobs[i].kind == kJobCliqueLgsBlock) {
-      const int64_t t = jobs[i].lds_ok ? lgs_tile_words(jobs[i].cap) : lgs_rows_offset(jobs[i].cap);
+      const int64_t t = jobs[i].lds_ok ? lgs_block_tile_words(jobs[i].cap) : lgs_rows_offset(jobs[i].cap);
       blk_tile = std::max(blk_tile, t);
       blk_vmax = std::max<int64_t>(blk_vmax, jobs[i].cap);
       if (!jobs[i].lds_ok) blk_hbm_rows = true;
