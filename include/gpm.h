@@ -168,6 +168,9 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     workgroup's LDS (up to 896 vertices with 160 KB, fewer when the
  *                     device's per-workgroup LDS is smaller) are searched by
  *                     a whole workgroup each; 0 = by one wave, rows in HBM
+ *   "lgs_lanes"       local-graph row build: lanes that scan one row's
+ *                     out-list together (4, 8, 16, 32 or 64 = a whole wave);
+ *                     fewer lanes put more rows in flight per wave
  *   "lgs_max"         roots with more out-neighbours (64..2048) use the
  *                     edge kernel
  *   "lgs_split"       1 = split the heaviest roots (5-cliques per wave,
@@ -211,7 +214,7 @@ const char *gpm_last_error(const gpm_ctx *ctx);
  *                     that takes at least "tune_min_ms" (default 20), try the
  *                     knob values of its search space (LDS tile, waves per
  *                     CU, chunk, leaf mode, set-op mode, granularity,
- *                     renaming) by
+ *                     renaming, row-build lanes) by
  *                     coordinate descent -- every trial must return the same
  *                     count, else GPM_E_DEVICE -- and reuse the fastest
  *                     values on later calls of that triple

@@ -173,7 +173,7 @@ struct KernelArgs {
   int64_t wave_stride;             // int32 words of fbuf per wave
   int32_t lds_words;               // int32 words of dynamic LDS per wave
   int32_t lgs_tile;                // local graphs up to this size use LDS
-  int32_t pad0;
+  int32_t lgs_lg;                  // local-graph row build: log2 of the lanes per row (6: a wave)
   int32_t* zbuf;                   // 4-cycle kernel: per-workgroup cursor regions
   int64_t zstride;                 // words of zbuf per workgroup
 };

@@ -392,16 +392,20 @@ __device__ __forceinline__ int32_t lgs_hash_get(const TH* H, int32_t bits, int32
 }
 
 // Rows of a local graph: R_i = positions in L of N+(L[i]) ∩ L, for rows
-// i = first, first + step, ... (the calling wave owns these rows; its lanes
-// walk the row's out-list 64 elements at a time and look each element up in
-// the hash H of L).  Out-lists are sorted, so a row stops at the first batch
-// whose elements all exceed max(L).  With BITS the hits are set in R (rows
-// of W words); the number of hits is returned either way (per lane).
-// With `next` (the workgroup path), rows are taken from that LDS counter one
-// at a time instead (first and step unused), so waves that drew short rows
-// take more of them.  With SC every hit (triangle u, L[i], L[j]) adds 1 to
-// the per-row counters lc[i] and lc[j] (edges u-L[i], u-L[j]) and to
-// tri[p], p the DAG position of the element (edge L[i]-L[j]).
+// i = first, first + step, ... (the calling wave owns these rows).  The wave
+// scans 64 >> lg rows at once, one per group of 2^lg lanes (lg = 6: one row
+// at a time with the whole wave; short out-lists leave most of a wave's
+// lanes idle and its rows waiting one memory round trip each, which groups
+// of 16 or 8 lanes overlap); a group walks its row's out-list 2^lg elements
+// at a time and looks each element up in the hash H of L.  Out-lists are
+// sorted, so a row stops at the first batch whose elements all exceed
+// max(L).  With BITS the hits are set in R (rows of W words); the number of
+// hits is returned either way (per lane).  With `next` (the workgroup path),
+// rows are taken from that LDS counter a round at a time instead (first and
+// step unused), so waves that drew short rows take more of them.  With SC
+// every hit (triangle u, L[i], L[j]) adds 1 to the per-row counters lc[i]
+// and lc[j] (edges u-L[i], u-L[j]) and to tri[p], p the DAG position of the
+// element (edge L[i]-L[j]).
 template <bool CE, bool BITS, bool SC = false, typename TL, typename TH, typename TR,
           typename TC = int32_t>
 __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ rp,
@@ -410,58 +414,77 @@ __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ r
                                                    int32_t bits, TR* R, int32_t first,
                                                    int32_t step, ElemCounter& ec,
                                                    int32_t* next = nullptr, TC* lc = nullptr,
-                                                   unsigned int* tri = nullptr) {
-  constexpr int U = 4;  // batches of 64 elements whose loads are in flight together
+                                                   unsigned int* tri = nullptr, int32_t lg = 6) {
+  constexpr int U = 4;  // batches of a group's lanes whose loads are in flight together
   const int l = lane_id();
+  const int32_t GL = 1 << lg;      // lanes per group
+  const int32_t G = 64 >> lg;      // rows per round
+  const int32_t g = l >> lg;       // this lane's group
+  const int32_t q = l & (GL - 1);  // its lane within the group
+  const uint64_t gmask = (lg == 6 ? ~0ull : ((1ull << GL) - 1ull)) << (g * GL);
+  const int32_t gs = next ? 1 : step;  // row distance between the groups of a round
   const int32_t lmax = uni(L[d - 1]);
   auto take = [&]() -> int32_t {
     int32_t r = 0;
-    if (l == 0) r = atomicAdd(next, 1);
+    if (l == 0) r = atomicAdd(next, G);
     return uni(__shfl(r, 0, 64));
   };
   uint64_t hits = 0;
-  int32_t i = next ? take() : first;
-  int64_t nb = 0, ne = 0;  // bounds of the next row, loaded one row ahead
-  if (i < d) {
-    const int32_t v = uni(L[i]);
-    nb = uni64(rp[v]);
-    ne = uni64(rp[v + 1]);
-  }
-  while (i < d) {
-    const int64_t b = nb, e = ne;
-    const int32_t in = next ? take() : i + step;
-    if (in < d) {
-      const int32_t v = uni(L[in]);
-      nb = uni64(rp[v]);
-      ne = uni64(rp[v + 1]);
+  int32_t ib = next ? take() : first;  // first row of the round (uniform)
+  int64_t nb = 0, ne = 0;              // bounds of the group's row, loaded a round ahead
+  {
+    const int32_t ig = ib + g * gs;
+    if (ib < d && ig < d) {
+      const int32_t v = L[ig];
+      nb = rp[v];
+      ne = rp[v + 1];
     }
-    if (CE) ec.elems += (uint64_t)(e - b);
-    for (int64_t pb = b; pb < e; pb += 64 * U) {
+  }
+  while (ib < d) {
+    const int32_t i = ib + g * gs;  // this group's row; (b, e) = (0, 0) if i >= d
+    const int64_t b = nb, e = ne;
+    const int32_t in = next ? take() : ib + G * step;
+    nb = 0;
+    ne = 0;
+    {
+      const int32_t ig = in + g * gs;
+      if (in < d && ig < d) {
+        const int32_t v = L[ig];
+        nb = rp[v];
+        ne = rp[v + 1];
+      }
+    }
+    if (CE) ec.elems += (uint64_t)(e - b) * (uint64_t)G;  // summed over the lanes / 64
+    bool live = b < e;
+    for (int64_t pb = b;; pb += (int64_t)GL * U) {
       int32_t x[U];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int64_t p = pb + q * 64 + l;
-        x[q] = p < e ? col[p] : INT_MAX;
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = pb + u * GL + q;
+        x[u] = (live && p < e) ? col[p] : INT_MAX;
       }
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (x[q] <= lmax) {
-          const int32_t j = lgs_hash_get(H, bits, x[q]);
+      for (int u = 0; u < U; ++u) {
+        if (x[u] <= lmax) {
+          const int32_t j = lgs_hash_get(H, bits, x[u]);
           if (j >= 0) {
             ++hits;
             if (BITS) atomicOr(&R[(size_t)i * W + (j >> 6)], 1ull << (j & 63));
             if (SC) {
               atomicAdd(&lc[i], 1);
               atomicAdd(&lc[j], 1);
-              atomicAdd(&tri[pb + q * 64 + l], 1u);
+              atomicAdd(&tri[pb + u * GL + q], 1u);
             }
           }
         }
       }
-      // out-lists are sorted: once every element exceeds max(L), none further can hit
-      if (wave_ballot(x[U - 1] <= lmax) == 0ull) break;
+      // a row ends at its last element or at the first batch whose elements
+      // all exceed max(L) (none further can hit)
+      const uint64_t more = wave_ballot(x[U - 1] <= lmax);
+      live = live && (more & gmask) != 0ull && pb + (int64_t)GL * U < e;
+      if (wave_ballot(live) == 0ull) break;
     }
-    i = in;
+    ib = in;
   }
   return hits;
 }
@@ -653,7 +676,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                int32_t u, int32_t d, int32_t part,
                                                int32_t parts, bool ordered, TL* L, TP* P,
                                                TH* H, TR* R, unsigned int* tri,
-                                               ElemCounter& ec) {
+                                               ElemCounter& ec, int32_t lg) {
   const int l = lane_id();
   const int32_t W = (d + 63) >> 6;
   const int32_t bits = lgs_hash_bits(d);
@@ -673,12 +696,14 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   if (k == 3) {
     if (part != 0) return 0;
     if constexpr (!SC) {
-      return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
+      return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr,
+                                       (int32_t*)nullptr, nullptr, lg);
     } else {
       // triangle scatter: P holds the per-row counters (edges u-L[i])
       for (int32_t i = l; i < d; i += 64) P[i] = 0;
       wave_sync_mem();
-      lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr, P, tri);
+      lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr, P, tri,
+                                      lg);
       wave_sync_mem();
       const int64_t e0 = rp[u];
       for (int32_t i = l; i < d; i += 64)
@@ -686,7 +711,8 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       return 0;
     }
   }
-  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec);
+  lgs_build_rows<CE, true>(rp, col, L, d, W, H, bits, R, 0, 1, ec, nullptr, (int32_t*)nullptr,
+                          nullptr, lg);
   wave_sync_mem();
   uint64_t c = 0;
   int32_t running;
@@ -814,7 +840,8 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
                                      const int32_t* __restrict__ col, int k, int32_t u,
                                      int32_t d, int32_t part, int32_t parts, bool ordered,
                                      int32_t* lds, int32_t* tmp, int32_t* next, int32_t* sort_area,
-                                     unsigned int* tri, unsigned long long* Rg, ElemCounter& ec) {
+                                     unsigned int* tri, unsigned long long* Rg, ElemCounter& ec,
+                                     int32_t lg) {
   constexpr int NT = kBlockWaves * 64;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
@@ -842,19 +869,21 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   if (k == 3) {
     if (part != 0) return 0;
     if (!tri)
-      return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next);
+      return lgs_build_rows<CE, false>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next,
+                                       (int32_t*)nullptr, nullptr, lg);
     // triangle scatter: P holds the per-row counters (edges u-L[i])
     for (int32_t i = tid; i < d; i += NT) P[i] = 0;
     __syncthreads();
     lgs_build_rows<CE, false, true>(rp, col, L, d, W, H, bits, R, wv, kBlockWaves, ec, next, P,
-                                    tri);
+                                    tri, lg);
     __syncthreads();
     const int64_t e0 = rp[u];
     for (int32_t i = tid; i < d; i += NT)
       if (P[i]) atomicAdd(&tri[e0 + i], (unsigned int)P[i]);
     return 0;
   }
-  lgs_build_rows<CE, true>(rp, col, L, d, S, H, bits, R, wv, kBlockWaves, ec, next);
+  lgs_build_rows<CE, true>(rp, col, L, d, S, H, bits, R, wv, kBlockWaves, ec, next,
+                          (int32_t*)nullptr, nullptr, lg);
   __syncthreads();
   uint64_t c = 0;
   // pairs (i, j) with j in row i, enumerated through a prefix over row sizes
@@ -1757,14 +1786,14 @@ __device__ __forceinline__ void lgs_tasks(const Job& J, const KernelArgs& a, int
       unsigned long long* H = (unsigned long long*)(my + lgs_hash_offset(a.lgs_tile));
       unsigned long long* R = (unsigned long long*)(my + lgs_rows_offset(a.lgs_tile));
       acc[0] += clique_lgs<CE, SC>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
-                                   J.tri, ec);
+                                   J.tri, ec, a.lgs_lg);
     } else {
       int32_t* L = fb;
       int32_t* Pp = fb + J.cap;
       unsigned long long* H = (unsigned long long*)(fb + lgs_hash_offset(J.cap));
       unsigned long long* R = (unsigned long long*)(fb + lgs_rows_offset(J.cap));
       acc[0] += clique_lgs<CE, SC>(rp, col, k, u, d, part, parts, J.ordered != 0, L, Pp, H, R,
-                                   J.tri, ec);
+                                   J.tri, ec, a.lgs_lg);
     }
   }
 }
@@ -1991,12 +2020,12 @@ gpm_lgs_block(KernelArgs a) {
         acc[0] += clique_lgs_block<CE, true>(J.rp, J.col, J.k, u, d, part, parts,
                                              J.ordered != 0, blk_lds, scan_tmp, &row_next,
                                              blk_lds + a.lds_words - kBlockWaves * kSortWords,
-                                             J.tri, Rg, ec);
+                                             J.tri, Rg, ec, a.lgs_lg);
       else
         acc[0] += clique_lgs_block<CE, false>(J.rp, J.col, J.k, u, d, part, parts,
                                               J.ordered != 0, blk_lds, scan_tmp, &row_next,
                                               blk_lds + a.lds_words - kBlockWaves * kSortWords,
-                                              J.tri, nullptr, ec);
+                                              J.tri, nullptr, ec, a.lgs_lg);
       __syncthreads();  // the next root reuses the local graph's LDS
     }
   }

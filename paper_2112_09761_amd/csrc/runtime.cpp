@@ -175,6 +175,7 @@ struct gpm_ctx {
   int64_t opt_clique_algo = 0, opt_lgs_tile = 128, opt_lgs_max = kLgsMaxVertices;
   int64_t opt_lgs_split = 1, opt_leaf_cap = 128, opt_cycle4_algo = 0;
   int64_t opt_lgs_block = 1;                    // large roots: one workgroup each
+  int64_t opt_lgs_lanes = 64;                   // local-graph row build: lanes that scan one row
   int64_t opt_decompose = 1;                    // counting-only decomposition of named motifs
   int64_t opt_cycle4_mode = 0;                  // 0 cost model, 1 hash tasks only, 2 direct windows
   int64_t opt_cycle4_batch = kCycHashCap * 2 / 3;  // wedges per 4-cycle hash task
@@ -1101,7 +1102,8 @@ static gpm_status add_count_jobs(gpm_ctx* c, Graph& g, const gpm_pattern& p, int
 
 
 // ---------------------------------------------------------------------------
-// autotuner: task granularity, chunk size, LDS tile, waves per CU, leaf mode
+// autotuner: task granularity, chunk size, LDS tile, waves per CU, leaf mode,
+// set-op mode, row-build lanes
 // ---------------------------------------------------------------------------
 
 static int64_t* knob(gpm_ctx* c, const std::string& k) {
@@ -1113,6 +1115,7 @@ static int64_t* knob(gpm_ctx* c, const std::string& k) {
   if (k == "rename") return &c->opt_rename;
   if (k == "lds_tile") return &c->opt_lds_tile;
   if (k == "setop") return &c->opt_setop;
+  if (k == "lgs_lanes") return &c->opt_lgs_lanes;
   return nullptr;
 }
 
@@ -1122,7 +1125,8 @@ static std::vector<std::pair<std::string, std::vector<int64_t>>> tune_space(cons
                                                                              int mode) {
   const bool clique = p.n_edges == p.k * (p.k - 1) / 2;
   if (clique && p.k <= 5)
-    return {{"lgs_tile", {128, 64, 192}}, {"waves_per_cu", {0, 16, 32}}, {"chunk", {0, 2}}};
+    return {{"lgs_tile", {128, 64, 192}}, {"waves_per_cu", {0, 16, 32}}, {"chunk", {0, 2}},
+            {"lgs_lanes", {64, 32}}};
   if (clique) return {{"lds_tile", {0, 256, 128}}, {"chunk", {0, 4, 16}}, {"waves_per_cu", {16, 12}}};
   (void)mode;
   return {{"leaf_cap", {128, 0, 32, 512}}, {"setop", {0, 1, 2}}, {"chunk", {0, 2, 32}},
@@ -1658,6 +1662,7 @@ static gpm_status launch_group(gpm_ctx* c, Slot& s, JobPlanSet& js, bool fission
     const bool uses_lds = (L.kinds & (kKindClique | kKindCliqueLgs | kKindTriScatter)) != 0;
     a.lds_words = uses_lds ? lds_words : 0;
     a.lgs_tile = lgs_T;
+    a.lgs_lg = 31 - __builtin_clz((unsigned)c->opt_lgs_lanes);
     a.zbuf = (L.kinds & kKindCycleBlock) ? zbuf : nullptr;
     a.zstride = zstride;
     size_t lb = uses_lds ? lds_bytes : 0;
@@ -2157,6 +2162,10 @@ gpm_status gpm_set_option(gpm_ctx* c, const char* key, int64_t v) {
   else if (k == "clique_algo") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "clique_algo 0..2"); c->opt_clique_algo = v; }
   else if (k == "lgs_split") c->opt_lgs_split = v != 0;
   else if (k == "lgs_block") c->opt_lgs_block = v != 0;
+  else if (k == "lgs_lanes") {
+    if (v < 4 || v > 64 || (v & (v - 1))) return fail(c, GPM_E_INVAL, "lgs_lanes 4, 8, 16, 32 or 64");
+    c->opt_lgs_lanes = v;
+  }
   else if (k == "decompose") c->opt_decompose = v != 0;
   else if (k == "edge_terms") { if (v < 0 || v > 1) return fail(c, GPM_E_INVAL, "edge_terms 0..1"); c->opt_edge_terms = v; }
   else if (k == "cycle4_mode") { if (v < 0 || v > 2) return fail(c, GPM_E_INVAL, "cycle4_mode 0..2"); c->opt_cycle4_mode = v; }

@@ -190,7 +190,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                           ("lgs_split", [0]), ("leaf_cap", [0, 1, 4096]),
                           ("rename", [0]), ("cycle4_algo", [1, 2]), ("decompose", [0]),
                           ("edge_terms", [1]), ("cycle4_mode", [1, 2]), ("setop", [1, 2, 3]),
-                          ("cycle4_batch", [16, 1 << 20])]:
+                          ("cycle4_batch", [16, 1 << 20]), ("lgs_lanes", [32, 8, 4])]:
             for v in vals:
                 ctx.set_option(opt, v)
                 for n, e in exp.items():
@@ -201,7 +201,7 @@ def test_tuning_options_do_not_change_counts(ctx, oracle):
                                  "lgs_tile": 128, "lgs_max": 2048, "lgs_split": 1,
                                  "leaf_cap": 128, "rename": 1, "cycle4_algo": 0,
                                  "decompose": 1, "edge_terms": 0, "cycle4_mode": 0, "setop": 0,
-                                 "cycle4_batch": 8192}[opt])
+                                 "cycle4_batch": 8192, "lgs_lanes": 64}[opt])
     finally:
         ctx.unload(gid)
 
@@ -275,13 +275,16 @@ def test_workgroup_local_graphs(ctx, parts, k5_both):
     gid = ctx.load(g)
     try:
         ctx.set_option("lgs_tile", 64)
-        for k in (3, 4, 5):
-            for blk in ((1, 0) if (k < 5 or k5_both) else (1,)):
-                ctx.set_option("lgs_block", blk)
-                assert ctx.count(gid, synth_clique(k)) == esym(parts, k), (k, blk)
+        for lanes in (64, 16, 4):
+            ctx.set_option("lgs_lanes", lanes)
+            for k in (3, 4, 5):
+                for blk in ((1, 0) if (k < 5 or k5_both) else (1,)):
+                    ctx.set_option("lgs_block", blk)
+                    assert ctx.count(gid, synth_clique(k)) == esym(parts, k), (k, blk, lanes)
     finally:
         ctx.set_option("lgs_block", 1)
         ctx.set_option("lgs_tile", 128)
+        ctx.set_option("lgs_lanes", 64)
         ctx.unload(gid)
 
 
@@ -296,7 +299,8 @@ def test_workgroup_rmat_options(ctx, oracle):
     try:
         ctx.set_option("lgs_tile", 64)
         for opt, v in [("lgs_split", 0), ("lgs_split", 1), ("count_elements", 1),
-                       ("count_elements", 0), ("lgs_block", 0), ("lgs_block", 1)]:
+                       ("lgs_lanes", 16), ("count_elements", 0), ("lgs_lanes", 4),
+                       ("lgs_block", 0), ("lgs_block", 1), ("lgs_lanes", 8)]:
             ctx.set_option(opt, v)
             for k in (3, 4, 5):
                 assert ctx.count(gid, synth_clique(k)) == exp[k], (opt, v, k)
@@ -311,6 +315,7 @@ def test_workgroup_rmat_options(ctx, oracle):
         ctx.set_option("lgs_split", 1)
         ctx.set_option("count_elements", 0)
         ctx.set_option("lgs_block", 1)
+        ctx.set_option("lgs_lanes", 64)
         ctx.unload(gid)
 
 
