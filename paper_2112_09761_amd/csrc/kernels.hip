@@ -524,21 +524,31 @@ __device__ __forceinline__ uint64_t lgs_pairs5(const TP* P, const TR* R, int32_t
     if constexpr (WC <= 16) {
       // both loops unrolled: every word index is static.  Bits are taken from
       // the two 32-bit halves of each word (cheaper find-first and clear), and
-      // the row index is kept opaque so the row's reads share one base
-      // address with small immediate offsets.
+      // the row offset within the half-word's block of rows is kept opaque so
+      // the row's reads share one base address with small immediate offsets.
 #pragma unroll
       for (int x = 0; x < WC; ++x) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           uint32_t m = (uint32_t)(M[x] >> (32 * h));
+          const TR* Rxh = R + (size_t)(x * 64 + 32 * h) * WC;
           while (m) {
-            int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
+            uint32_t b = __builtin_ctz(m);
             m &= m - 1u;
-            asm volatile("" : "+v"(lrow));
+            asm("" : "+v"(b));
             // rows < 2^24: the 24-bit multiply is exact and full rate
-            const TR* Rl = R + __umul24((uint32_t)lrow, (uint32_t)WC);
+            const TR* Rl = Rxh + __umul24(b, (uint32_t)WC);
 #pragma unroll
-            for (int y = ORD ? x : 0; y < WC; ++y) cp += (uint32_t)__popcll(M[y] & Rl[y]);
+            for (int y = ORD ? x : 0; y < WC; ++y) {
+              const uint64_t t = M[y] & Rl[y];
+              // ordered: row l has bits above l only (see lgs_edge5)
+              if (!(ORD && y == x && h == 1)) {
+                cp = (uint32_t)__builtin_popcount((uint32_t)t) + cp;
+                asm("" : "+v"(cp));
+              }
+              cp = (uint32_t)__builtin_popcount((uint32_t)(t >> 32)) + cp;
+              asm("" : "+v"(cp));
+            }
             if (CE) ec.words += (uint64_t)(WC - (ORD ? x : 0));
           }
         }
@@ -583,14 +593,29 @@ __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       uint32_t m = (uint32_t)(M[x] >> (32 * h));
+      const unsigned long long* Rxh = R + (size_t)(x * 64 + 32 * h) * S;
       while (m) {
-        int32_t lrow = x * 64 + 32 * h + __builtin_ctz(m);
+        uint32_t b = __builtin_ctz(m);
         m &= m - 1u;
-        asm volatile("" : "+v"(lrow));
-        const unsigned long long* Rl = R + __umul24((uint32_t)lrow, (uint32_t)S);
+        // opaque row offset: the row's reads share one base address with
+        // small immediate offsets
+        asm("" : "+v"(b));
+        const unsigned long long* Rl = Rxh + __umul24(b, (uint32_t)S);
 #pragma unroll
         for (int y = x; y < WC; ++y)
-          if (y < W) cp += (uint32_t)__popcll(M[y] & Rl[y]);
+          if (y < W) {
+            const uint64_t t = M[y] & Rl[y];
+            // row l = x * 64 + 32 * h + b has bits above l only: with l in
+            // the upper half of word x, the lower half of t is zero.  Each
+            // popcount adds to cp in turn (the empty asm keeps the sum a
+            // chain of accumulating popcounts, not a tree of extra adds).
+            if (!(y == x && h == 1)) {
+              cp = (uint32_t)__builtin_popcount((uint32_t)t) + cp;
+              asm("" : "+v"(cp));
+            }
+            cp = (uint32_t)__builtin_popcount((uint32_t)(t >> 32)) + cp;
+            asm("" : "+v"(cp));
+          }
       }
     }
   }
