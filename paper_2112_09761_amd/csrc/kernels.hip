@@ -872,11 +872,25 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   const int wv = tid >> 6;
   const int32_t W = (d + 63) >> 6;
   const int32_t S = HBM ? W : (int32_t)lgs_block_stride_words(W);  // row stride
-  const int32_t bits = lgs_hash_bits(d);
+  // hash of L: at least 2d slots (load factor <= 1/2), up to four times as
+  // many where the launch's tile area (all of the LDS below the sort area,
+  // sized for its largest root) still holds them beside the rows: most
+  // elements of a row's out-list are not in L, and a lookup that misses
+  // ends after fewer probes in an emptier table
+  int32_t bits = lgs_hash_bits(d);
+  {
+    const int64_t avail = sort_area - lds;
+    const int64_t rows = HBM ? 0 : 2 * (int64_t)d * S;
+    for (int e = 0; e < 2; ++e) {
+      if (lgs_hash_offset(d) + 2 * (int64_t(1) << (bits + 1)) + rows > avail) break;
+      ++bits;
+    }
+  }
   int32_t* L = lds;
   int32_t* P = lds + d;
   unsigned long long* H = (unsigned long long*)(lds + lgs_hash_offset(d));
-  unsigned long long* R = HBM ? Rg : (unsigned long long*)(lds + lgs_rows_offset(d));
+  unsigned long long* R =
+      HBM ? Rg : (unsigned long long*)(lds + lgs_hash_offset(d) + 2 * (int64_t(1) << bits));
   const int32_t* Nu = col + rp[u];
   for (int32_t i = tid; i < (1 << bits); i += NT) H[i] = 0ull;
   if (k > 3)
