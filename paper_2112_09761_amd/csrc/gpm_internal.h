@@ -181,7 +181,8 @@ struct KernelArgs {
 // Local-graph tile of T vertices, in int32 words: L[T] | P[T + 1] | (pad to
 // 8 B) | H[lgs_hash_slots(T)] uint64 (hash of L: vertex -> position) |
 // R[T * ceil(T / 64)] uint64 (bitmap rows).  A root of d <= T vertices uses
-// the first lgs_hash_slots(d) slots of H.
+// the first lgs_hash_slots(d) slots of H, or up to four times as many where H
+// has them (an emptier table ends lookups that miss sooner).
 __host__ __device__ inline int64_t lgs_hash_slots(int64_t d) {
   int64_t s = 2;
   while (s < 2 * d) s <<= 1;  // load factor <= 1/2: every probe sequence meets an empty slot

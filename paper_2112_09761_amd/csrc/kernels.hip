@@ -704,7 +704,13 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
                                                ElemCounter& ec, int32_t lg) {
   const int l = lane_id();
   const int32_t W = (d + 63) >> 6;
-  const int32_t bits = lgs_hash_bits(d);
+  // hash of L: at least 2d slots, up to four times as many within the tile's
+  // hash area (the slots between H and R, sized for the tile's T >= d)
+  int32_t bits = lgs_hash_bits(d);
+  {
+    const int64_t area = ((const char*)R - (const char*)H) / 8;
+    for (int e = 0; e < 2 && (int64_t(1) << (bits + 1)) <= area; ++e) ++bits;
+  }
   const int32_t* Nu = col + rp[u];
   for (int32_t i = l; i < d; i += 64) L[i] = Nu[i];
   for (int32_t i = l; i < (1 << bits); i += 64) H[i] = 0ull;
