@@ -31,8 +31,8 @@ WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
 # for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
 # the kernel sources they were taken on (and that launch) only; else null.
-TRAFFIC = {"sources_sha256": "86f576b7179e56f5a840a2cd0da0f4198aa413e12de50eb2d4e84fbb43c1af80",
-           "k": 5, "kinds": 1 << 7, "fetch_kib": 1904233.9, "write_kib": 3938.2,
+TRAFFIC = {"sources_sha256": "ac6264263edca52c2c0e48b0e7555549938c10c0d5df5f2a2c5f8fa2403ea755",
+           "k": 5, "kinds": 1 << 7, "fetch_kib": 1850811.9, "write_kib": 2914.2,
            "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
 
@@ -90,17 +90,16 @@ def measured_traffic(k, kinds):
 
 
 # gpm_list on the listing workload: the same two counter passes (KiB per
-# dispatch), valid for the sources they were taken on (earlier sources than
-# the current ones: reported as null until taken again)
-LIST_TRAFFIC = {"sources_sha256": "20c3cf868f5a382a9a7641b60533fe0893e6c01998856ae6169957da11ce16fb",
-                "fetch_kib": 160388.1, "write_kib": 5050520.3,
+# dispatch), valid for the sources they were taken on
+LIST_TRAFFIC = {"sources_sha256": "ac6264263edca52c2c0e48b0e7555549938c10c0d5df5f2a2c5f8fa2403ea755",
+                "fetch_kib": 161496.5, "write_kib": 5049164.0,
                 "fetch_factor": 2.0, "write_factor": 1.0}
 
 
 # gpm_cycle_block (4-cycles) on the Chung-Lu workload: the same two counter
 # passes (KiB per dispatch), valid for the sources they were taken on
-CYC_TRAFFIC = {"sources_sha256": "86f576b7179e56f5a840a2cd0da0f4198aa413e12de50eb2d4e84fbb43c1af80",
-               "fetch_kib": 128875918.8, "write_kib": 19540046.4,
+CYC_TRAFFIC = {"sources_sha256": "ac6264263edca52c2c0e48b0e7555549938c10c0d5df5f2a2c5f8fa2403ea755",
+               "fetch_kib": 129508524.3, "write_kib": 19544474.8,
                "fetch_factor": 2.0, "write_factor": 1.0}
 
 
