@@ -489,6 +489,44 @@ __device__ __forceinline__ uint64_t lgs_build_rows(const int64_t* __restrict__ r
   return hits;
 }
 
+// Local edges t0 .. t1-1 of a local graph (rows of W words at a stride of
+// S, row-size prefix P over its d rows), in order: f(i, j) for each.  The
+// first is located through P, each next one as the next bit of the same row
+// (a search again only where the row ends).
+template <typename TP, typename TR, typename F>
+__device__ __forceinline__ void lgs_edge_walk(const TP* P, const TR* R, int32_t d, int32_t W,
+                                              int32_t S, int32_t t0, int32_t t1, F&& f) {
+  int32_t i = 0, j = 0;
+  for (int32_t t = t0; t < t1; ++t) {
+    bool found = false;
+    if (t > t0) {  // edge t - 1 is (i, j)
+      const TR* Rc = R + (size_t)i * S;
+      int32_t w = (j + 1) >> 6;
+      if (w < W) {
+        uint64_t bm = Rc[w] & (~0ull << ((j + 1) & 63));
+        while (!bm && ++w < W) bm = Rc[w];
+        if (bm) {
+          j = w * 64 + __builtin_ctzll(bm);
+          found = true;
+        }
+      }
+    }
+    if (!found) {
+      i = upper_bound(P + 1, d, t);
+      int32_t r = t - P[i];
+      const TR* Rc = R + (size_t)i * S;
+      int32_t w = 0;
+      for (;; ++w) {
+        const int32_t pc = __popcll(Rc[w]);
+        if (r < pc) break;
+        r -= pc;
+      }
+      j = w * 64 + select64(Rc[w], r);
+    }
+    f(i, j);
+  }
+}
+
 // L: d ints, P: d + 1 ints, R: d * W uint64 (W = ceil(d / 64)).
 // Sub-task `part` of `parts` handles its share of the local edges (i, j), so
 // the heaviest roots are spread over several waves (each rebuilds the local
@@ -624,7 +662,8 @@ __device__ __forceinline__ uint32_t lgs_edge5(const unsigned long long* R, int32
 
 // The workgroup kernel's 5-clique pair phase with lanes balanced by work:
 // each wave takes batches of kSortBatch consecutive local edges (p0 .. p1-1,
-// enumerated through the row-size prefix P), keys every edge by a
+// enumerated row by row; the row-size prefix P locates a lane's first
+// edge), keys every edge by a
 // logarithm of its cost estimate |R_i & R_j| · (words from j's on) — four
 // keys per octave, 0..63 — counting-sorts the batch by key in its LDS area
 // (ids, cnt), then counts the sorted edges 64 at a time, so that the lanes of
@@ -643,22 +682,43 @@ __device__ __forceinline__ uint64_t lgs_pairs5_sorted(const int32_t* P,
     cnt[l] = 0;
     wave_sync_mem();
     int32_t key[K], pid[K];
+    // this lane's K consecutive local edges t0 .. t0 + K - 1: the first found
+    // through the row-size prefix, each next one as the next bit of the same
+    // row (a search again only where the row ends)
+    const int32_t t0 = base + l * K;
+    int32_t i = 0, j = 0;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-      const int32_t t = base + q * 64 + l;
+      const int32_t t = t0 + q;
       key[q] = 64;
       pid[q] = 0;
       if (t < p1) {
-        const int32_t i = upper_bound(P + 1, d, t);
-        int32_t r = t - P[i];
-        const unsigned long long* Ri = R + (size_t)i * S;
-        int32_t w = 0;
-        for (;; ++w) {
-          const int32_t pc = __popcll(Ri[w]);
-          if (r < pc) break;
-          r -= pc;
+        bool found = false;
+        if (q > 0) {  // edge t - 1 is (i, j)
+          const unsigned long long* Rc = R + (size_t)i * S;
+          int32_t w = (j + 1) >> 6;
+          if (w < W) {
+            uint64_t bm = Rc[w] & (~0ull << ((j + 1) & 63));
+            while (!bm && ++w < W) bm = Rc[w];
+            if (bm) {
+              j = w * 64 + __builtin_ctzll(bm);
+              found = true;
+            }
+          }
         }
-        const int32_t j = w * 64 + select64(Ri[w], r);
+        if (!found) {
+          i = upper_bound(P + 1, d, t);
+          int32_t r = t - P[i];
+          const unsigned long long* Rc = R + (size_t)i * S;
+          int32_t w = 0;
+          for (;; ++w) {
+            const int32_t pc = __popcll(Rc[w]);
+            if (r < pc) break;
+            r -= pc;
+          }
+          j = w * 64 + select64(Rc[w], r);
+        }
+        const unsigned long long* Ri = R + (size_t)i * S;
         const unsigned long long* Rj = R + (size_t)j * S;
         const int jw = (j + 1) >> 6;
         int32_t m = 0;
@@ -764,19 +824,11 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
   const int32_t p0 = (int32_t)((int64_t)pairs * part / parts);
   const int32_t p1 = (int32_t)((int64_t)pairs * (part + 1) / parts);
   if (k == 4) {
-    for (int32_t tb = p0; tb < p1; tb += 64) {
-      int32_t t = tb + l;
-      if (t >= p1) continue;
-      int32_t i = upper_bound(P + 1, d, t);
-      int32_t r = t - P[i];
+    // each lane a contiguous slice of the local edges, walked row by row
+    const int32_t per = (p1 - p0 + 63) >> 6;
+    const int32_t t0 = min(p1, p0 + l * per), t1 = min(p1, t0 + per);
+    lgs_edge_walk(P, R, d, W, W, t0, t1, [&](int32_t i, int32_t j) {
       const TR* Ri = R + (size_t)i * W;
-      int32_t w = 0;
-      for (;; ++w) {
-        int32_t pc = __popcll(Ri[w]);
-        if (r < pc) break;
-        r -= pc;
-      }
-      const int32_t j = w * 64 + select64(Ri[w], r);
       const TR* Rj = R + (size_t)j * W;
       // ordered: R_j has bits only above j
       const int32_t x0 = ordered ? ((j + 1) >> 6) : 0;
@@ -784,7 +836,7 @@ __device__ __forceinline__ uint64_t clique_lgs(const int64_t* __restrict__ rp,
       for (int32_t x = x0; x < W; ++x) cp += (uint32_t)__popcll(Ri[x] & Rj[x]);
       c += cp;
       if (CE) ec.words += (uint64_t)(W - x0);
-    }
+    });
     return c;
   }
   // k = 5: for every local edge (i, j) (one per lane) and every l in
@@ -955,24 +1007,18 @@ __device__ __forceinline__ uint64_t clique_lgs_block(const int64_t* __restrict__
   const int32_t p0 = (int32_t)((int64_t)pairs * part / parts);
   const int32_t p1 = (int32_t)((int64_t)pairs * (part + 1) / parts);
   if (k == 4) {
-    for (int32_t t = p0 + tid; t < p1; t += NT) {
-      const int32_t i = upper_bound(P + 1, d, t);
-      int32_t r = t - P[i];
+    // each thread a contiguous slice of the local edges, walked row by row
+    const int32_t per = (p1 - p0 + NT - 1) / NT;
+    const int32_t t0 = min(p1, p0 + tid * per), t1 = min(p1, t0 + per);
+    lgs_edge_walk(P, R, d, W, S, t0, t1, [&](int32_t i, int32_t j) {
       const unsigned long long* Ri = R + (size_t)i * S;
-      int32_t w = 0;
-      for (;; ++w) {
-        const int32_t q = __popcll(Ri[w]);
-        if (r < q) break;
-        r -= q;
-      }
-      const int32_t j = w * 64 + select64(Ri[w], r);
       const unsigned long long* Rj = R + (size_t)j * S;
       const int32_t x0 = ordered ? ((j + 1) >> 6) : 0;
       uint32_t cp = 0;
       for (int32_t x = x0; x < W; ++x) cp += (uint32_t)__popcll(Ri[x] & Rj[x]);
       c += cp;
       if (CE) ec.words += (uint64_t)(W - x0);
-    }
+    });
     return c;
   }
   if (!CE && ordered) {
