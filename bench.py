@@ -31,8 +31,8 @@ WORD_OP_PEAK_TOPS = 256 * 64 * 2.4e9 / 4 / 1e12
 # a plain device copy of 1 GiB (--copy-calibration): FETCH_SIZE reads 0.5 GiB
 # for it (factor 2.0), WRITE_SIZE 1 GiB (factor 1.0).  The figures hold for
 # the kernel sources they were taken on (and that launch) only; else null.
-TRAFFIC = {"sources_sha256": "ac6264263edca52c2c0e48b0e7555549938c10c0d5df5f2a2c5f8fa2403ea755",
-           "k": 5, "kinds": 1 << 7, "fetch_kib": 1850811.9, "write_kib": 2914.2,
+TRAFFIC = {"sources_sha256": "a2a57d884de457215b6a386dcdf1294a3f9e53688a4565386683db919aff8356",
+           "k": 5, "kinds": 1 << 7, "fetch_kib": 1914028.1, "write_kib": 3938.2,
            "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ["kernels.hip", "gpm_internal.h", "runtime.cpp"]
 
@@ -91,15 +91,15 @@ def measured_traffic(k, kinds):
 
 # gpm_list on the listing workload: the same two counter passes (KiB per
 # dispatch), valid for the sources they were taken on
-LIST_TRAFFIC = {"sources_sha256": "ac6264263edca52c2c0e48b0e7555549938c10c0d5df5f2a2c5f8fa2403ea755",
-                "fetch_kib": 161496.5, "write_kib": 5049164.0,
+LIST_TRAFFIC = {"sources_sha256": "a2a57d884de457215b6a386dcdf1294a3f9e53688a4565386683db919aff8356",
+                "fetch_kib": 160709.2, "write_kib": 5046334.9,
                 "fetch_factor": 2.0, "write_factor": 1.0}
 
 
 # gpm_cycle_block (4-cycles) on the Chung-Lu workload: the same two counter
 # passes (KiB per dispatch), valid for the sources they were taken on
-CYC_TRAFFIC = {"sources_sha256": "ac6264263edca52c2c0e48b0e7555549938c10c0d5df5f2a2c5f8fa2403ea755",
-               "fetch_kib": 129508524.3, "write_kib": 19544474.8,
+CYC_TRAFFIC = {"sources_sha256": "a2a57d884de457215b6a386dcdf1294a3f9e53688a4565386683db919aff8356",
+               "fetch_kib": 128985724.3, "write_kib": 19542572.4,
                "fetch_factor": 2.0, "write_factor": 1.0}
 
 
